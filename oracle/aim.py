@@ -1,0 +1,226 @@
+"""Adaptive integral method, eq. (11): L ~ L_NR + W H P (Sec. III-A).
+
+TEST INFRASTRUCTURE ONLY (see oracle/__init__.py).
+
+The paper names the pieces (P projects basis functions onto a uniform grid,
+H is the grid convolution done by FFT, W interpolates back, L_NR is the
+precorrected near field) and leaves the details to [Bleszynski1996] and
+[Phillips1997].  Readings used on both sides of this project:
+
+  * grid: N_c nodes per axis, spacing h_c = max(ext_c/(N_c-3), H/4) with
+    H = max_c ext_c/(N_c-3) (ext = vertex bounding box), centred on the box;
+  * expansion order M = 2: the stencil of a basis function is the 3x3x3 block
+    of nodes centred on the node nearest its centre (RWG: mean of the two
+    triangle centroids; pulse: centroid);
+  * stencil weights match every moment (r - r0)^alpha, 0 <= alpha_c <= 2, of the
+    source about the stencil centre r0; for the Cartesian components of an RWG
+    function and for the pulse h_t / A_t;
+  * W = P^T (Galerkin testing);
+  * grid kernel G(Delta) = e^{-j k0 R}/(4 pi R), R = |Delta o h|, and G(0) = 0;
+    aperiodic convolution by zero padding to 2 N_c per axis;
+  * near zone: stencil centres within Chebyshev index distance 3;
+  * precorrection: L_NR[m,n] = L[m,n] - sum_c P_c[:,m]^T G P_c[:,n] on near pairs.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+import scipy.sparse as sp
+
+from .quad import tri_points
+from .rwg import RWG
+
+NEAR_CHEB = 3
+
+
+@dataclass
+class Grid:
+    N: np.ndarray       # (3,) int nodes per axis
+    h: np.ndarray       # (3,) spacing
+    origin: np.ndarray  # (3,)
+
+    @property
+    def n_nodes(self):
+        return int(np.prod(self.N))
+
+    def node_pos(self, idx):
+        return self.origin + np.asarray(idx) * self.h
+
+    def linear(self, idx):
+        idx = np.asarray(idx)
+        return (idx[..., 2] * self.N[1] + idx[..., 1]) * self.N[0] + idx[..., 0]
+
+
+def make_grid(verts, N):
+    N = np.asarray(N, dtype=np.int64)
+    lo, hi = verts.min(axis=0), verts.max(axis=0)
+    ext = hi - lo
+    H = np.max(ext / (N - 3))
+    h = np.maximum(ext / (N - 3), H / 4.0)
+    center = 0.5 * (lo + hi)
+    origin = center - h * (N - 1) / 2.0
+    return Grid(N, h, origin)
+
+
+def basis_centres(g: RWG):
+    rc = 0.5 * (g.centroid[g.tplus] + g.centroid[g.tminus])
+    return rc, g.centroid.copy()
+
+
+def stencil_centre(grid: Grid, pts):
+    idx = np.rint((pts - grid.origin) / grid.h).astype(np.int64)
+    if np.any(idx < 1) or np.any(idx > grid.N - 2):
+        raise ValueError("stencil leaves the grid")
+    return idx
+
+
+OFFS = np.array([(dx, dy, dz) for dz in (-1, 0, 1) for dy in (-1, 0, 1) for dx in (-1, 0, 1)])
+ALPHAS = np.array([(ax, ay, az) for az in range(3) for ay in range(3) for ax in range(3)])
+
+
+def _moment_matrix(h):
+    """V[alpha, node] = prod_c (offset_c h_c)^alpha_c for the 27 stencil nodes."""
+    d = OFFS * h[None, :]
+    return np.prod(d[None, :, :] ** ALPHAS[:, None, :], axis=2)
+
+
+def stencil_weights(grid: Grid, g: RWG, order=5):
+    """Solve the 27x27 moment systems for every RWG (3 components) and pulse.
+
+    Returns (cidx_e (N_E,3), wE (N_E, 3 comps, 27), cidx_t (N_T,3), wT (N_T, 27)).
+    """
+    rcE, rcT = basis_centres(g)
+    cE, cT = stencil_centre(grid, rcE), stencil_centre(grid, rcT)
+    V = _moment_matrix(grid.h)
+    Vt = g.verts[g.tris]
+    pts, w = tri_points(Vt, order)                       # (N_T, q, 3), (N_T, q)
+    # RWG components: moments accumulated from both triangles
+    momE = np.zeros((g.n_e, 3, 27))
+    for i in range(3):
+        n = g.tri_edge[:, i]
+        r0 = grid.node_pos(cE[n])                         # (N_T,3)
+        rel = pts - r0[:, None, :]
+        mono = np.prod(rel[:, :, None, :] ** ALPHAS[None, None, :, :], axis=3)   # (N_T,q,27)
+        f = (g.tri_sign[:, i] * g.length[n] / (2.0 * g.area))[:, None, None] * (pts - Vt[:, i][:, None, :])
+        np.add.at(momE, n, np.einsum('tq,tqc,tqa->tca', w, f, mono))
+    r0 = grid.node_pos(cT)
+    rel = pts - r0[:, None, :]
+    mono = np.prod(rel[:, :, None, :] ** ALPHAS[None, None, :, :], axis=3)
+    momT = np.einsum('tq,tqa->ta', w, mono) / g.area[:, None]
+    wE = np.linalg.solve(V[None, None], momE[..., None])[..., 0]
+    wT = np.linalg.solve(V[None], momT[..., None])[..., 0]
+    return cE, wE, cT, wT
+
+
+def projection_matrices(grid: Grid, g: RWG):
+    """Sparse P_x, P_y, P_z (nodes x N_E) and P_rho (nodes x N_T)."""
+    cE, wE, cT, wT = stencil_weights(grid, g)
+    nodesE = grid.linear(cE[:, None, :] + OFFS[None])      # (N_E,27)
+    nodesT = grid.linear(cT[:, None, :] + OFFS[None])
+    colsE = np.repeat(np.arange(g.n_e), 27)
+    colsT = np.repeat(np.arange(g.n_t), 27)
+    Pc = [sp.csr_matrix((wE[:, c, :].ravel(), (nodesE.ravel(), colsE)), shape=(grid.n_nodes, g.n_e))
+          for c in range(3)]
+    Pr = sp.csr_matrix((wT.ravel(), (nodesT.ravel(), colsT)), shape=(grid.n_nodes, g.n_t))
+    return Pc, Pr, (cE, wE, nodesE), (cT, wT, nodesT)
+
+
+def grid_kernel_value(grid: Grid, k0, delta):
+    """G(Delta) = e^{-j k0 R}/(4 pi R), R = |Delta o h|; G(0) = 0."""
+    R = np.sqrt(np.sum((np.asarray(delta) * grid.h) ** 2, axis=-1))
+    with np.errstate(divide='ignore', invalid='ignore'):
+        v = np.exp(-1j * k0 * R) / (4.0 * np.pi * R)
+    return np.where(R > 0, v, 0.0)
+
+
+def circulant_kernel(grid: Grid, k0):
+    """G on the zero-padded (2N)^3 grid, index order [z, y, x]; offset N_c unused (0)."""
+    axes = []
+    for c in range(3):
+        n2 = 2 * grid.N[c]
+        o = np.arange(n2)
+        o = np.where(o < grid.N[c], o, o - n2).astype(float)
+        o[grid.N[c]] = np.nan
+        axes.append(o)
+    Z, Y, X = np.meshgrid(axes[2], axes[1], axes[0], indexing='ij')
+    d = np.stack([X, Y, Z], axis=-1)
+    G = grid_kernel_value(grid, k0, np.nan_to_num(d, nan=0.0))
+    G[np.isnan(d).any(axis=-1)] = 0.0
+    return G
+
+
+def convolve_fft(grid: Grid, Ghat, src):
+    """Aperiodic grid convolution phi(g) = sum_g' G(g - g') src(g') via FFT (src in node order)."""
+    Nx, Ny, Nz = grid.N
+    S = np.zeros((2 * Nz, 2 * Ny, 2 * Nx), dtype=complex)
+    S[:Nz, :Ny, :Nx] = src.reshape(Nz, Ny, Nx)
+    out = np.fft.ifftn(Ghat * np.fft.fftn(S))
+    return out[:Nz, :Ny, :Nx].ravel()
+
+
+def convolve_direct(grid: Grid, k0, src):
+    """Brute-force sum over all node pairs (tiny grids only)."""
+    Nx, Ny, Nz = grid.N
+    idx = np.stack(np.meshgrid(np.arange(Nx), np.arange(Ny), np.arange(Nz), indexing='ij'), -1)
+    idx = idx.transpose(2, 1, 0, 3).reshape(-1, 3)        # node order x fastest
+    d = idx[:, None, :] - idx[None, :, :]
+    Gm = grid_kernel_value(grid, k0, d)
+    return Gm @ src
+
+
+def near_pairs(cA, cB, symmetric=True):
+    """Index pairs (m, n) whose stencil centres are within Chebyshev distance NEAR_CHEB."""
+    from scipy.spatial import cKDTree
+    tA = cKDTree(cA.astype(float))
+    tB = tA if symmetric else cKDTree(cB.astype(float))
+    pairs = tA.query_ball_tree(tB, r=NEAR_CHEB + 0.5, p=np.inf)
+    m = np.repeat(np.arange(len(pairs)), [len(p) for p in pairs])
+    n = np.concatenate([np.asarray(p, dtype=np.int64) for p in pairs]) if len(pairs) else np.zeros(0, np.int64)
+    return m, n
+
+
+def grid_part(grid: Grid, k0, cA, wA, cB, wB, m, n):
+    """sum over components and stencil nodes of wA[m] G(node_m - node_n) wB[n] (per pair)."""
+    out = np.zeros(m.size, dtype=complex)
+    d = OFFS[:, None, :] - OFFS[None, :, :]                 # (27,27,3)
+    for lo in range(0, m.size, 20000):
+        s = slice(lo, lo + 20000)
+        delta = (cA[m[s]] - cB[n[s]])[:, None, None, :] + d[None]
+        Gs = grid_kernel_value(grid, k0, delta)             # (B,27,27)
+        if wA.ndim == 3:
+            out[s] = np.einsum('bcx,bxy,bcy->b', wA[m[s]], Gs, wB[n[s]], optimize=True)
+        else:
+            out[s] = np.einsum('bx,bxy,by->b', wA[m[s]], Gs, wB[n[s]], optimize=True)
+    return out
+
+
+@dataclass
+class AIMOperator:
+    grid: Grid
+    k0: float
+    Pc: list
+    Pr: object
+    Ghat: np.ndarray
+    LA_nr: object     # sparse N_E x N_E
+    Lphi_nr: object   # sparse N_T x N_T
+
+    def apply_LA(self, j):
+        far = sum(P.T @ convolve_fft(self.grid, self.Ghat, P @ j) for P in self.Pc)
+        return self.LA_nr @ j + far
+
+    def apply_Lphi(self, q):
+        return self.Lphi_nr @ q + self.Pr.T @ convolve_fft(self.grid, self.Ghat, self.Pr @ q)
+
+
+def build_aim(g: RWG, grid: Grid, k0, LA_exact, Lphi_exact):
+    """O-aim from exact near entries.  LA_exact(m, n) / Lphi_exact(t, u) return entries."""
+    Pc, Pr, (cE, wE, _), (cT, wT, _) = projection_matrices(grid, g)
+    Ghat = np.fft.fftn(circulant_kernel(grid, k0))
+    m, n = near_pairs(cE, cE)
+    vA = LA_exact(m, n) - grid_part(grid, k0, cE, wE, cE, wE, m, n)
+    t, u = near_pairs(cT, cT)
+    vP = Lphi_exact(t, u) - grid_part(grid, k0, cT, wT, cT, wT, t, u)
+    LA_nr = sp.csr_matrix((vA, (m, n)), shape=(g.n_e, g.n_e))
+    Lphi_nr = sp.csr_matrix((vP, (t, u)), shape=(g.n_t, g.n_t))
+    return AIMOperator(grid, k0, Pc, Pr, Ghat, LA_nr, Lphi_nr)
