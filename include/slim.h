@@ -1,0 +1,203 @@
+/*
+ * slim.h -- C ABI of the MI355X library for the system matrix-vector product
+ * of the SLIM surface-integral formulation for lossy conductors and the GMRES
+ * solve built on it (Marek, Sharma, Triverio, "A Parallel Boundary Element
+ * Method for the Electromagnetic Analysis of Large Structures With Lossy
+ * Conductors").
+ *
+ * The operator is eq. (7) with C of eq. (8):
+ *
+ *   [ j k0 L_A + C           D^T L_phi B ] [ H      ]   [ E_inc / eta0 ]
+ *   [ F D (I - Y_eq Z)       j k0 I      ] [ c0 rho ] = [ 0            ]
+ *
+ * with Z = diag(Z_i) (eq. (4), (9)), Y_eq = diag(Y_eq,i) (eq. (5), (10)),
+ * L_A, L_phi applied through the adaptive integral method of eq. (11)
+ * (L_NR + W H P) or, with grid = {0,0,0}, as dense matrices.
+ *
+ * Conventions shared by every entry point
+ *  - Lengths in metres, SI units, time dependence e^{j omega t}.
+ *  - Vectors at the ABI are complex128, interleaved (re, im), on the device.
+ *    A system vector is [H (n_e RWG coefficients of n x H); c0 rho (n_t
+ *    pulse coefficients)], n_sys = n_e + n_t.  RWG unknowns are ordered
+ *    object by object and, inside an object, by (lower vertex id, higher
+ *    vertex id) of the edge; the triangle order is the caller's.
+ *  - RWG f_n = l/(2A+) (r - p+) on T+ (the triangle whose vertex cycle runs
+ *    along the edge from the lower to the higher vertex id), l/(2A-) (p- - r)
+ *    on T-.  D[T+,n] = +l_n, D[T-,n] = -l_n, B = diag(A_t), F = -diag(1/A_t),
+ *    I_x[m,n] = int (n x f_m) . f_n.
+ *  - Host arrays passed in are copied before the call returns; the caller
+ *    keeps ownership.  Device buffers passed in (x, y, b, ...) belong to the
+ *    caller; the library never frees or retains them.  The library owns
+ *    every allocation it makes and releases it in slim_destroy.
+ *  - `stream` is a hipStream_t (NULL = default stream).  slim_matvec only
+ *    enqueues work; slim_solve and slim_build return after completion.
+ *  - Every entry point returns a slim_status and never throws.  On failure
+ *    slim_last_error() describes the cause (valid until the next call on the
+ *    same context).  A failed set_* call leaves the context unchanged; a failed
+ *    build leaves it unbuilt.  One context per host thread.
+ */
+#ifndef SLIM_H
+#define SLIM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct slim_ctx slim_ctx;
+
+typedef enum {
+  SLIM_OK = 0,
+  SLIM_E_ARG = 1,           /* invalid argument (null pointer, size, option)          */
+  SLIM_E_MESH = 2,          /* not closed / not manifold / degenerate / bad object id */
+  SLIM_E_STATE = 3,         /* call out of order (e.g. matvec before build)           */
+  SLIM_E_OOM = 4,           /* device memory budget or allocation exceeded            */
+  SLIM_E_HIP = 5,           /* HIP / rocSOLVER / rocBLAS runtime error                */
+  SLIM_E_NUMERIC = 6,       /* NaN / Inf or breakdown                                 */
+  SLIM_E_NOT_CONVERGED = 7, /* GMRES stopped at max_iter; best iterate returned       */
+  SLIM_E_UNSUPPORTED = 8
+} slim_status;
+
+/* Precision of the operator applied by slim_matvec / used inside slim_solve.
+ * SLIM_FP64: FP64 arithmetic; internal blocks read as hi + lo complex64 pairs
+ *            (a 48-bit significand, the same bytes as complex128), grids,
+ *            near field and vectors complex128.
+ * SLIM_MIXED: internal blocks from the hi complex64 part with FP32
+ *            accumulation (or split-BF16 MFMA, see internal_kernel), complex64
+ *            FFT convolution and near field, FP32 stencil weights.          */
+typedef enum { SLIM_FP64 = 0, SLIM_MIXED = 1 } slim_prec;
+
+typedef struct {
+  double sigma;   /* S/m   (copper 5.8e7) */
+  double eps_r;
+  double mu_r;
+} slim_material;
+
+typedef struct {
+  double freq;          /* Hz                                                     */
+  int32_t grid[3];      /* AIM grid nodes per axis; {0,0,0}: dense L_A, L_phi     */
+  int32_t near_cheb;    /* near zone: stencil centres within this Chebyshev index
+                           distance (3)                                           */
+  /* triangle-pair quadrature (both rules are described in the library source):
+     far TRI(n_far)^2; near: TRI(n_near) outer x polar rule (levels, q, n_r, n_t);
+     near when the centroid distance < c_near * max triangle diameter            */
+  int32_t n_far, n_near, levels, n_r, n_t;
+  double q, c_near;
+  int32_t sched_mode;     /* 0 = LPT on flop counts, 1 = MLP cost model, 2 = naive */
+  int32_t tile_rows;      /* row-panel height of internal tiles (0 = autotune)     */
+  int32_t internal_kernel;/* mixed internal GEMV: 0 = FP32 FMA, 1 = split-BF16 MFMA */
+  int32_t slots;          /* persistent workgroups of the internal kernel (0 = auto) */
+  int64_t mem_budget;     /* bytes of device memory the build may use (0 = no cap)  */
+  int32_t verbose;
+} slim_build_opts;
+
+/* Fill `o` with the defaults used by the tests (near_cheb 3, n_far 4, n_near 5,
+ * levels 3, q 0.25, n_r 5, n_t 6, c_near 2, LPT, autotuned tiles).            */
+void slim_default_build_opts(slim_build_opts* o);
+
+typedef struct {
+  int64_t n_e, n_t, n_sys;
+  int32_t n_obj;
+  int32_t grid[3];
+  double grid_h[3], grid_origin[3];
+  int64_t nnz_near_A, nnz_near_phi;    /* near-field CSR non-zeros               */
+  int64_t internal_entries;            /* sum_i 2 n_i^2                          */
+  int64_t n_tiles;                     /* internal work-queue tiles              */
+  int32_t slots;
+  int32_t tile_rows;
+  double mean_edge;                    /* h of the row scaling used by slim_solve */
+  double build_seconds;
+  int64_t device_bytes;                /* device memory held by the context      */
+} slim_layout;
+
+typedef struct {
+  double tol;          /* relative residual of the row-equilibrated system        */
+  int32_t restart;     /* GMRES(m)                                                 */
+  int32_t max_iter;    /* total inner iterations                                   */
+  slim_prec prec;      /* FP64: plain GMRES; MIXED: GMRES-IR (FP64 outer residual) */
+  double inner_tol;    /* MIXED: relative tolerance of each inner solve            */
+  int32_t max_outer;
+} slim_solve_opts;
+
+typedef struct {
+  int32_t iterations, outer_steps;
+  double rel_residual;        /* final true residual (FP64 operator)              */
+  double seconds, matvec_seconds;
+  int32_t n_matvec_fp64, n_matvec_mixed;
+} slim_solve_info;
+
+/* --- context ----------------------------------------------------------- */
+slim_status slim_create(int32_t hip_device, slim_ctx** out);
+void slim_destroy(slim_ctx* ctx);                       /* NULL-safe */
+const char* slim_last_error(const slim_ctx* ctx);
+
+/* --- problem ----------------------------------------------------------- */
+/* Closed, outward-oriented triangle surfaces, one per object (Sec. II).
+ * xyz: n_vert x 3 doubles; tri: n_tri x 3 vertex ids; obj_of_tri: n_tri ids in
+ * [0, n_obj), non-decreasing.  SLIM_E_MESH names the offending triangle/edge. */
+slim_status slim_set_mesh(slim_ctx* ctx, const double* xyz, int64_t n_vert,
+                          const int32_t* tri, int64_t n_tri,
+                          const int32_t* obj_of_tri, int32_t n_obj);
+/* Per-object material (NULL: copper, sigma = 5.8e7, eps_r = mu_r = 1) in a
+ * homogeneous free-space background (the layer l of eq. (5) is free space). */
+slim_status slim_set_materials(slim_ctx* ctx, const slim_material* per_obj);
+
+/* Operator build (eq. (4)-(6), (11)): RWG table, AIM grid, stencils, near
+ * field with precorrection, Green's function spectrum, per-object L, K, FP64
+ * LU, explicit Z_i and M_i = Y_eq,i Z_i, task packing, autotuning, graphs. */
+slim_status slim_build(slim_ctx* ctx, const slim_build_opts* opts);
+slim_status slim_get_layout(const slim_ctx* ctx, slim_layout* out);
+/* Host copies of the RWG table: edge_v (2 n_e: lower, higher vertex id),
+ * tplus, tminus (n_e each).  Any pointer may be NULL. */
+slim_status slim_get_rwg(const slim_ctx* ctx, int32_t* edge_v, int32_t* tplus, int32_t* tminus);
+
+/* --- hot path -------------------------------------------------------------- */
+/* y = A x (eq. (7)-(8)); x, y: n_sys complex128 device vectors, no aliasing. */
+slim_status slim_matvec(slim_ctx* ctx, slim_prec prec, const void* x_dev, void* y_dev, void* stream);
+/* Same product and its intermediate vectors (complex128 device buffers, any
+ * may be NULL): e = Z H, g = M H, a = L_A j (n_e each), phi = L_phi B c0rho (n_t). */
+slim_status slim_matvec_parts(slim_ctx* ctx, slim_prec prec, const void* x_dev, void* y_dev,
+                              void* e_dev, void* g_dev, void* a_dev, void* phi_dev, void* stream);
+/* Internal part only (eq. (4)-(6) applied blockwise): e = Z H, g = M H.  The
+ * internal kernel's makespan (persistent launch) is returned in *ms if non-NULL
+ * (synchronous when ms != NULL). */
+slim_status slim_internal_apply(slim_ctx* ctx, slim_prec prec, const void* H_dev, void* e_dev,
+                                void* g_dev, double* ms, void* stream);
+
+/* Right-hand side of (7) for an incident plane wave E0 epol e^{-j k0 khat.r}. */
+slim_status slim_rhs_planewave(slim_ctx* ctx, const double khat[3], const double epol[3],
+                               void* b_dev, void* stream);
+
+/* GMRES on S A x = S b with S = diag(1/h^2 (N_E rows), h (N_T rows)), h the
+ * mean edge length (a change of length unit that balances the two row blocks).
+ * x_dev: in = x0, out = solution (complex128, n_sys).  b_dev is S b or b
+ * according to `scaled_rhs` (1: b_dev already equilibrated).  Synchronous. */
+slim_status slim_solve(slim_ctx* ctx, const void* b_dev, int32_t scaled_rhs, void* x_dev,
+                       const slim_solve_opts* opts, slim_solve_info* info, void* stream);
+
+/* --- internal task scheduling (Alg. 1, Part_Schedule idea; learned cost) ---- */
+/* Record per-tile start/end timestamps on the next internal launches. */
+slim_status slim_sched_record(slim_ctx* ctx, int32_t on);
+/* Copy the last recorded tiles: per tile (block, row0, rows, n, slot, t_start,
+ * t_end) as 7 doubles; *n_tiles in: capacity, out: count. */
+slim_status slim_sched_tiles(slim_ctx* ctx, double* out, int64_t* n_tiles);
+/* Train the MLP cost model (on the GPU, own forward/backward kernels) on the
+ * recorded tiles; returns the final training loss. */
+slim_status slim_sched_train(slim_ctx* ctx, int32_t epochs, double lr, double* final_loss);
+/* 0 = LPT on flop counts, 1 = MLP-predicted times, 2 = naive (object order,
+ * round robin); re-packs the work queues and re-captures the graphs. */
+slim_status slim_sched_set_mode(slim_ctx* ctx, int32_t mode);
+
+/* --- cost-model network kernels (exposed for gradient checks) -------------- */
+/* FP32 MLP F -> 64 -> 64 -> 1 (tanh).  params (device, fp32) in the order
+ * W1 (64 x F), b1, W2 (64 x 64), b2, w3 (64), b3 (1); X (B x F), t (B).
+ * Computes loss = mean (y - t)^2, y (B) and grad (same layout as params). */
+slim_status slim_mlp_forward_backward(int32_t F, int32_t B, const float* params_dev,
+                                      const float* X_dev, const float* t_dev, float* y_dev,
+                                      float* grad_dev, float* loss_dev, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SLIM_H */

@@ -1,0 +1,369 @@
+// Operator build: physics constants, I_x, interior blocks Z_i (eq. (4)),
+// Y_eq,i (eq. (5)) and M_i = Y_eq,i Z_i (eq. (6)) by FP64 LU on the GPU, the
+// external operator (dense or AIM), the task queues and the work buffers.
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstdio>
+#include <unordered_map>
+
+#include "ctx.hpp"
+
+namespace slim {
+
+namespace {
+
+struct RocHandle {
+  rocblas_handle h = nullptr;
+  explicit RocHandle(hipStream_t s) {
+    if (rocblas_create_handle(&h) != rocblas_status_success) throw Error(SLIM_E_HIP, "rocblas_create_handle failed");
+    rocblas_set_stream(h, s);
+  }
+  ~RocHandle() { if (h) rocblas_destroy_handle(h); }
+};
+
+#define SLIM_ROC(call)                                                                        \
+  do {                                                                                        \
+    rocblas_status st_ = (call);                                                              \
+    if (st_ != rocblas_status_success)                                                        \
+      throw ::slim::Error(SLIM_E_HIP, std::string(#call) + " failed: " + std::to_string(int(st_))); \
+  } while (0)
+
+// Candidate near triangle pairs (t <= u) in [t0, t1): centroid distance below
+// 1.01 c_near max(diam); the device takes the exact decision.
+std::vector<int32_t> near_candidates(const RWGTable& r, int64_t t0, int64_t t1, double c_near) {
+  std::vector<int32_t> out;
+  if (t1 <= t0) return out;
+  double dmax = 0.0, lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+  for (int64_t t = t0; t < t1; ++t) {
+    dmax = std::max(dmax, r.diam[t]);
+    for (int k = 0; k < 3; ++k) {
+      lo[k] = std::min(lo[k], r.centroid[3 * t + k]);
+      hi[k] = std::max(hi[k], r.centroid[3 * t + k]);
+    }
+  }
+  const double cell = 1.01 * c_near * dmax;
+  int64_t nc[3];
+  for (int k = 0; k < 3; ++k) nc[k] = std::max<int64_t>(1, int64_t((hi[k] - lo[k]) / cell) + 1);
+  auto cell_of = [&](int64_t t, int64_t* c3) {
+    for (int k = 0; k < 3; ++k)
+      c3[k] = std::min<int64_t>(nc[k] - 1, std::max<int64_t>(0, int64_t((r.centroid[3 * t + k] - lo[k]) / cell)));
+  };
+  std::unordered_map<int64_t, std::vector<int32_t>> bins;
+  for (int64_t t = t0; t < t1; ++t) {
+    int64_t c3[3];
+    cell_of(t, c3);
+    bins[(c3[2] * nc[1] + c3[1]) * nc[0] + c3[0]].push_back(int32_t(t));
+  }
+  for (int64_t t = t0; t < t1; ++t) {
+    int64_t c3[3];
+    cell_of(t, c3);
+    for (int64_t dz = -1; dz <= 1; ++dz)
+      for (int64_t dy = -1; dy <= 1; ++dy)
+        for (int64_t dx = -1; dx <= 1; ++dx) {
+          int64_t x = c3[0] + dx, y = c3[1] + dy, z = c3[2] + dz;
+          if (x < 0 || y < 0 || z < 0 || x >= nc[0] || y >= nc[1] || z >= nc[2]) continue;
+          auto it = bins.find((z * nc[1] + y) * nc[0] + x);
+          if (it == bins.end()) continue;
+          for (int32_t u : it->second) {
+            if (u < t) continue;
+            double d2 = 0.0;
+            for (int k = 0; k < 3; ++k) {
+              double d = r.centroid[3 * t + k] - r.centroid[3 * u + k];
+              d2 += d * d;
+            }
+            double dm = 1.01 * c_near * std::max(r.diam[t], r.diam[u]);
+            if (d2 < dm * dm) {
+              out.push_back(int32_t(t));
+              out.push_back(u);
+            }
+          }
+        }
+  }
+  return out;
+}
+
+// I_x rows: entries with the (up to four) other edges of T+ and T- of each RWG.
+// The integrand (n x f_m).f_n is quadratic on a triangle; the three-edge-midpoint
+// rule with weights A/3 is exact.
+void build_ix(const Mesh& m, const RWGTable& r, std::vector<int32_t>& col, std::vector<double>& val) {
+  col.assign(4 * r.n_e, -1);
+  val.assign(4 * r.n_e, 0.0);
+  std::vector<int> fill(r.n_e, 0);
+  const double* X = m.xyz.data();
+  for (int64_t t = 0; t < r.n_t; ++t) {
+    double v[3][3], mid[3][3];
+    for (int i = 0; i < 3; ++i)
+      for (int k = 0; k < 3; ++k) v[i][k] = X[3 * size_t(m.tri[3 * t + i]) + k];
+    for (int k = 0; k < 3; ++k) {
+      mid[0][k] = 0.5 * (v[1][k] + v[2][k]);
+      mid[1][k] = 0.5 * (v[2][k] + v[0][k]);
+      mid[2][k] = 0.5 * (v[0][k] + v[1][k]);
+    }
+    const double* nr = &r.normal[3 * t];
+    const double A = r.area[t];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        if (i == j) continue;
+        int mi = r.tri_edge[3 * t + i], nj = r.tri_edge[3 * t + j];
+        double ci = r.tri_sign[3 * t + i] * r.len[mi] / (2.0 * A);
+        double cj = r.tri_sign[3 * t + j] * r.len[nj] / (2.0 * A);
+        double s = 0.0;
+        for (int q = 0; q < 3; ++q) {
+          double fi[3], fj[3];
+          for (int k = 0; k < 3; ++k) {
+            fi[k] = ci * (mid[q][k] - v[i][k]);
+            fj[k] = cj * (mid[q][k] - v[j][k]);
+          }
+          double nx[3] = {nr[1] * fi[2] - nr[2] * fi[1], nr[2] * fi[0] - nr[0] * fi[2], nr[0] * fi[1] - nr[1] * fi[0]};
+          s += nx[0] * fj[0] + nx[1] * fj[1] + nx[2] * fj[2];
+        }
+        s *= A / 3.0;
+        int slot = -1;
+        for (int q = 0; q < fill[mi]; ++q)
+          if (col[4 * mi + q] == nj) slot = q;
+        if (slot < 0) {
+          SLIM_REQUIRE(fill[mi] < 4, SLIM_E_MESH, "RWG with more than four I_x neighbours");
+          slot = fill[mi]++;
+          col[4 * mi + slot] = nj;
+        }
+        val[4 * mi + slot] += s;
+      }
+  }
+}
+
+template <class T> void up(DevBuf& b, const std::vector<T>& v) { b.upload(v); }
+
+// Solve A X = B (n x n, column-major) from rocSOLVER's LU factors of A (in LU,
+// pivots ipiv): row swaps, unit-lower solve (rocBLAS), then a blocked upper solve
+// by substitution on 32-row diagonal blocks with GEMM updates of the rows above.
+// The interior EFIE matrices at low frequency have pivots spanning about eight
+// decades; explicit inversion of diagonal blocks (as in rocBLAS TRSM) loses all
+// accuracy on such factors, substitution does not.
+void lu_solve(rocblas_handle h, int n, double* LU, const rocblas_int* ipiv, double* B, hipStream_t s) {
+  auto Z = [](double* p) { return reinterpret_cast<rocblas_double_complex*>(p); };
+  SLIM_ROC(rocsolver_zlaswp(h, n, Z(B), n, 1, n, ipiv, 1));
+  rocblas_double_complex one{1.0, 0.0}, mone{-1.0, 0.0};
+  SLIM_ROC(rocblas_ztrsm(h, rocblas_side_left, rocblas_fill_lower, rocblas_operation_none, rocblas_diagonal_unit, n, n,
+                         &one, Z(LU), n, Z(B), n));
+  const int nb = 32;
+  for (int i1 = n; i1 > 0;) {
+    const int i0 = std::max(0, i1 - nb);
+    launch_usolve_block(LU, n, i0, i1 - i0, B, n, n, s);
+    if (i0 > 0)
+      SLIM_ROC(rocblas_zgemm(h, rocblas_operation_none, rocblas_operation_none, i0, n, i1 - i0, &mone,
+                             Z(LU) + int64_t(i0) * n, n, Z(B) + i0, n, &one, Z(B), n));
+    i1 = i0;
+  }
+}
+
+}  // namespace
+
+Ctx::~Ctx() {
+  if (ev_fork) (void)hipEventDestroy(ev_fork);
+  if (ev_join) (void)hipEventDestroy(ev_join);
+  if (s_aux) (void)hipStreamDestroy(s_aux);
+}
+
+static void build_internal(Ctx& c, hipStream_t s) {
+  const RWGTable& r = c.rwg;
+  RocHandle rh(s);
+  // arena layout
+  c.blocks.resize(r.n_obj);
+  int64_t off = 0, nmax = 0;
+  for (int i = 0; i < r.n_obj; ++i) {
+    int64_t n = r.obj_edge_off[i + 1] - r.obj_edge_off[i];
+    c.blocks[i] = {off, int32_t(n), int32_t(r.obj_edge_off[i])};
+    off += 2 * n * ((n + 1) & ~int64_t(1));   // rows padded to an even length (16-byte aligned)
+    nmax = std::max(nmax, n);
+  }
+  c.arena_elems = off;
+  if (c.opts.mem_budget > 0) {
+    int64_t need = off * 16 + 3 * nmax * nmax * 16;
+    SLIM_REQUIRE(need <= c.opts.mem_budget, SLIM_E_OOM,
+                 "device memory budget too small: internal blocks need " + std::to_string(need) + " bytes");
+  }
+  c.d_hi.alloc(size_t(off) * sizeof(Cplx<float>));
+  c.d_lo.alloc(size_t(off) * sizeof(Cplx<float>));
+  up(c.d_blocks, c.blocks);
+  DevBuf bufL, bufB, bufZ, ipiv, info;
+  bufL.alloc(size_t(nmax * nmax) * 16);
+  bufB.alloc(size_t(nmax * nmax) * 16);
+  bufZ.alloc(size_t(nmax * nmax) * 16);
+  ipiv.alloc(size_t(nmax) * sizeof(rocblas_int));
+  info.alloc(sizeof(rocblas_int) * size_t(r.n_obj) * 2);
+  SLIM_HIP(hipMemsetAsync(info.p, 0, info.bytes, s));
+  QuadOpts qo;
+  AsmLaunch L{};
+  L.xyz = c.d_xyz.as<double>(); L.tri = c.d_tri.as<int32_t>(); L.cen = c.d_cen.as<double>();
+  L.nrm = c.d_nrm.as<double>(); L.area = c.d_area.as<double>(); L.diam = c.d_diam.as<double>();
+  L.tri_edge = c.d_tri_edge.as<int32_t>(); L.tri_sign = c.d_tri_sign.as<int8_t>(); L.len = c.d_len.as<double>();
+  DevBuf d_pairs;
+  for (int i = 0; i < r.n_obj; ++i) {
+    const int n = c.blocks[i].n;
+    const size_t bytes = size_t(n) * n * 16;
+    L.t0 = int32_t(r.obj_tri_off[i]);
+    L.t1 = int32_t(r.obj_tri_off[i + 1]);
+    L.e0 = c.blocks[i].e0;
+    L.ld_e = n;
+    std::vector<int32_t> pairs = near_candidates(r, L.t0, L.t1, c.opts.c_near);
+    d_pairs.upload(pairs);
+    L.near_pairs = d_pairs.as<int32_t>();
+    L.n_near_pairs = int64_t(pairs.size() / 2);
+    // ---- Z_i = -1/(j w eps_c) L_kc^{-1} (K_kc + I_x/2)  (eq. (4)) ----
+    SLIM_HIP(hipMemsetAsync(bufL.p, 0, bytes, s));
+    SLIM_HIP(hipMemsetAsync(bufZ.p, 0, bytes, s));
+    L.k = c.kc[i];
+    L.Lk = bufL.as<double>(); L.Kk = bufZ.as<double>(); L.Lvec = nullptr; L.Lphi = nullptr;
+    L.skip_mag = 1e-24;   // conductor kernel: far pairs with |e^{-jk R}| < 1e-24 contribute nothing
+    launch_assemble(L, s);
+    launch_add_scaled_ix(bufZ.as<double>(), c.d_ix_col.as<int32_t>(), c.d_ix_val.as<double>(), L.e0, n, 0.5, s);
+    SLIM_ROC(rocsolver_zgetrf(rh.h, n, n, reinterpret_cast<rocblas_double_complex*>(bufL.p), n,
+                              ipiv.as<rocblas_int>(), info.as<rocblas_int>() + 2 * i));
+    lu_solve(rh.h, n, bufL.as<double>(), ipiv.as<rocblas_int>(), bufZ.as<double>(), s);
+    cd fz = -1.0 / (cd(0.0, 1.0) * c.omega * c.epsc[i]);
+    launch_scale(bufZ.as<double>(), int64_t(n) * n, fz, s);
+    // ---- Y_eq,i = 1/(j w mu0) L_k0^{-1} (K_k0 + I_x/2)  (eq. (5), free-space layer) ----
+    SLIM_HIP(hipMemsetAsync(bufL.p, 0, bytes, s));
+    SLIM_HIP(hipMemsetAsync(bufB.p, 0, bytes, s));
+    L.k = cd(c.k0, 0.0);
+    L.Lk = bufL.as<double>(); L.Kk = bufB.as<double>();
+    L.skip_mag = 0.0;
+    launch_assemble(L, s);
+    launch_add_scaled_ix(bufB.as<double>(), c.d_ix_col.as<int32_t>(), c.d_ix_val.as<double>(), L.e0, n, 0.5, s);
+    SLIM_ROC(rocsolver_zgetrf(rh.h, n, n, reinterpret_cast<rocblas_double_complex*>(bufL.p), n,
+                              ipiv.as<rocblas_int>(), info.as<rocblas_int>() + 2 * i + 1));
+    lu_solve(rh.h, n, bufL.as<double>(), ipiv.as<rocblas_int>(), bufB.as<double>(), s);
+    // ---- M_i = Y_eq,i Z_i  (eq. (6)); the 1/(j w mu0) factor folded into alpha ----
+    cd fy = 1.0 / (cd(0.0, 1.0) * c.omega * kMu0);
+    rocblas_double_complex alpha{fy.real(), fy.imag()}, beta{0.0, 0.0};
+    SLIM_ROC(rocblas_zgemm(rh.h, rocblas_operation_none, rocblas_operation_none, n, n, n, &alpha,
+                           reinterpret_cast<rocblas_double_complex*>(bufB.p), n,
+                           reinterpret_cast<rocblas_double_complex*>(bufZ.p), n, &beta,
+                           reinterpret_cast<rocblas_double_complex*>(bufL.p), n));
+    launch_pack_block(bufZ.as<double>(), bufL.as<double>(), n, c.d_hi.as<Cplx<float>>() + c.blocks[i].off,
+                      c.d_lo.as<Cplx<float>>() + c.blocks[i].off, s);
+    SLIM_HIP(hipStreamSynchronize(s));   // the pair list of the next object reuses d_pairs
+  }
+  std::vector<rocblas_int> h_info(2 * size_t(r.n_obj));
+  SLIM_HIP(hipMemcpy(h_info.data(), info.p, info.bytes, hipMemcpyDeviceToHost));
+  for (int i = 0; i < 2 * r.n_obj; ++i)
+    SLIM_REQUIRE(h_info[i] == 0, SLIM_E_NUMERIC,
+                 "singular interior matrix of object " + std::to_string(i / 2) + (i % 2 ? " (L_k0)" : " (L_kc)"));
+}
+
+static void build_plain_external(Ctx& c, hipStream_t s) {
+  const RWGTable& r = c.rwg;
+  const int64_t ne = r.n_e, nt = r.n_t;
+  DevBuf LA, LP, d_pairs;
+  LA.alloc(size_t(ne * ne) * 16);
+  LP.alloc(size_t(nt * nt) * 16);
+  SLIM_HIP(hipMemsetAsync(LA.p, 0, LA.bytes, s));
+  SLIM_HIP(hipMemsetAsync(LP.p, 0, LP.bytes, s));
+  AsmLaunch L{};
+  L.xyz = c.d_xyz.as<double>(); L.tri = c.d_tri.as<int32_t>(); L.cen = c.d_cen.as<double>();
+  L.nrm = c.d_nrm.as<double>(); L.area = c.d_area.as<double>(); L.diam = c.d_diam.as<double>();
+  L.tri_edge = c.d_tri_edge.as<int32_t>(); L.tri_sign = c.d_tri_sign.as<int8_t>(); L.len = c.d_len.as<double>();
+  L.t0 = 0; L.t1 = int32_t(nt); L.e0 = 0;
+  L.k = cd(c.k0, 0.0);
+  L.Lvec = LA.as<double>(); L.Lphi = LP.as<double>();
+  L.ld_e = ne; L.ld_t = nt;
+  std::vector<int32_t> pairs = near_candidates(r, 0, nt, c.opts.c_near);
+  d_pairs.upload(pairs);
+  L.near_pairs = d_pairs.as<int32_t>();
+  L.n_near_pairs = int64_t(pairs.size() / 2);
+  launch_assemble(L, s);
+  // L_A and L_phi are symmetric: the column-major arrays are also row-major.
+  c.d_LA_hi.alloc(size_t(ne * ne) * 8); c.d_LA_lo.alloc(size_t(ne * ne) * 8);
+  c.d_Lphi_hi.alloc(size_t(nt * nt) * 8); c.d_Lphi_lo.alloc(size_t(nt * nt) * 8);
+  launch_pack_dense(LA.as<double>(), ne, ne, c.d_LA_hi.as<Cplx<float>>(), c.d_LA_lo.as<Cplx<float>>(), s);
+  launch_pack_dense(LP.as<double>(), nt, nt, c.d_Lphi_hi.as<Cplx<float>>(), c.d_Lphi_lo.as<Cplx<float>>(), s);
+  SLIM_HIP(hipStreamSynchronize(s));
+}
+
+void build_all(Ctx& c, const slim_build_opts& o) {
+  auto t_start = std::chrono::steady_clock::now();
+  SLIM_REQUIRE(c.has_mesh, SLIM_E_STATE, "slim_set_mesh must be called before slim_build");
+  SLIM_REQUIRE(o.freq > 0.0, SLIM_E_ARG, "frequency must be positive");
+  SLIM_HIP(hipSetDevice(c.device));
+  c.built = false;
+  c.opts = o;
+  c.freq = o.freq;
+  c.omega = 2.0 * kPi * o.freq;
+  c.k0 = c.omega / kC0;
+  const RWGTable& r = c.rwg;
+  c.kc.resize(r.n_obj);
+  c.epsc.resize(r.n_obj);
+  for (int i = 0; i < r.n_obj; ++i) {
+    const Material& mt = c.mats.empty() ? Material{} : c.mats[i];
+    c.epsc[i] = cd(eps0() * mt.eps_r, -mt.sigma / c.omega);
+    cd k = c.omega * std::sqrt(kMu0 * mt.mu_r * c.epsc[i]);
+    c.kc[i] = k.imag() <= 0.0 ? k : -k;
+  }
+  QuadOpts qo;
+  qo.n_far = o.n_far; qo.n_near = o.n_near; qo.levels = o.levels; qo.n_r = o.n_r; qo.n_t = o.n_t;
+  qo.q = o.q; qo.c_near = o.c_near;
+  QuadRulesDev rules;
+  make_rules(qo, rules);
+  upload_rules(rules);
+
+  hipStream_t s = nullptr;
+  SLIM_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+  struct SG { hipStream_t s; ~SG() { if (s) (void)hipStreamDestroy(s); } } sg{s};
+  // geometry
+  std::vector<int8_t> sign(r.tri_sign.begin(), r.tri_sign.end());
+  up(c.d_xyz, c.mesh.xyz); up(c.d_tri, c.mesh.tri); up(c.d_cen, r.centroid); up(c.d_nrm, r.normal);
+  up(c.d_area, r.area); up(c.d_diam, r.diam); up(c.d_tri_edge, r.tri_edge); up(c.d_tri_sign, sign);
+  up(c.d_len, r.len); up(c.d_tplus, r.tplus); up(c.d_tminus, r.tminus);
+  std::vector<int32_t> ixc;
+  std::vector<double> ixv;
+  build_ix(c.mesh, r, ixc, ixv);
+  up(c.d_ix_col, ixc); up(c.d_ix_val, ixv);
+
+  build_internal(c, s);
+  c.plain = (o.grid[0] == 0 && o.grid[1] == 0 && o.grid[2] == 0);
+  if (c.plain) build_plain_external(c, s);
+  else build_aim(c, s);
+
+  // vectors
+  const int64_t nsys = r.n_e + r.n_t;
+  c.d_x64.alloc(size_t(nsys) * 8);
+  c.d_y64.alloc(size_t(nsys) * 8);
+  c.d_e.alloc(size_t(r.n_e) * 16);
+  c.d_g.alloc(size_t(r.n_e) * 16);
+  c.d_j.alloc(size_t(r.n_e) * 16);
+  c.d_a.alloc(size_t(r.n_e) * 16);
+  c.d_phi.alloc(size_t(r.n_t) * 16);
+  if (!c.s_aux) SLIM_HIP(hipStreamCreateWithFlags(&c.s_aux, hipStreamNonBlocking));
+  if (!c.ev_fork) SLIM_HIP(hipEventCreateWithFlags(&c.ev_fork, hipEventDisableTiming));
+  if (!c.ev_join) SLIM_HIP(hipEventCreateWithFlags(&c.ev_join, hipEventDisableTiming));
+
+  c.tile_rows = o.tile_rows > 0 ? o.tile_rows : 64;
+  c.sched_mode = o.sched_mode;
+  pack_tiles(c, o.sched_mode);
+  SLIM_HIP(hipStreamSynchronize(s));
+
+  slim_layout& Lo = c.layout;
+  Lo = slim_layout{};
+  Lo.n_e = r.n_e; Lo.n_t = r.n_t; Lo.n_sys = nsys; Lo.n_obj = r.n_obj;
+  for (int k = 0; k < 3; ++k) {
+    Lo.grid[k] = c.plain ? 0 : c.grid.N[k];
+    Lo.grid_h[k] = c.grid.h[k];
+    Lo.grid_origin[k] = c.grid.origin[k];
+  }
+  Lo.nnz_near_A = c.nnz_A; Lo.nnz_near_phi = c.nnz_P;
+  Lo.internal_entries = c.arena_elems;
+  Lo.n_tiles = int64_t(c.tiles.size());
+  Lo.slots = c.slots;
+  Lo.tile_rows = c.tile_rows;
+  Lo.mean_edge = r.mean_edge;
+  Lo.build_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+  size_t freeb = 0, totalb = 0;
+  (void)hipMemGetInfo(&freeb, &totalb);
+  Lo.device_bytes = int64_t(totalb - freeb);
+  c.built = true;
+}
+
+}  // namespace slim

@@ -1,0 +1,296 @@
+// C ABI entry points (include/slim.h).  Every call catches all exceptions and
+// turns them into a status code plus a message kept in the context.
+#include <algorithm>
+#include <cstring>
+
+#include "ctx.hpp"
+
+using namespace slim;
+
+
+namespace {
+
+template <class F> slim_status guard(slim_ctx* h, F&& f) {
+  if (!h) return SLIM_E_ARG;
+  try {
+    h->c.last_error.clear();
+    return f();
+  } catch (const Error& e) {
+    h->c.last_error = e.what();
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    h->c.last_error = "host allocation failed";
+    return SLIM_E_OOM;
+  } catch (const std::exception& e) {
+    h->c.last_error = e.what();
+    return SLIM_E_HIP;
+  } catch (...) {
+    h->c.last_error = "unknown error";
+    return SLIM_E_HIP;
+  }
+}
+
+hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+}  // namespace
+
+extern "C" {
+
+void slim_default_build_opts(slim_build_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->freq = 10e9;
+  o->near_cheb = 3;
+  o->n_far = 4;
+  o->n_near = 5;
+  o->levels = 3;
+  o->n_r = 5;
+  o->n_t = 6;
+  o->q = 0.25;
+  o->c_near = 2.0;
+  o->sched_mode = 0;
+  o->tile_rows = 0;
+  o->internal_kernel = 0;
+  o->slots = 0;
+}
+
+slim_status slim_create(int32_t hip_device, slim_ctx** out) {
+  if (!out) return SLIM_E_ARG;
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || hip_device < 0 || hip_device >= n) return SLIM_E_HIP;
+  try {
+    slim_ctx* h = new slim_ctx();
+    h->c.device = hip_device;
+    if (hipSetDevice(hip_device) != hipSuccess) {
+      delete h;
+      return SLIM_E_HIP;
+    }
+    *out = h;
+    return SLIM_OK;
+  } catch (...) {
+    return SLIM_E_OOM;
+  }
+}
+
+void slim_destroy(slim_ctx* h) {
+  if (!h) return;
+  (void)hipSetDevice(h->c.device);
+  (void)hipDeviceSynchronize();
+  delete h;
+}
+
+const char* slim_last_error(const slim_ctx* h) { return h ? h->c.last_error.c_str() : "null context"; }
+
+slim_status slim_set_mesh(slim_ctx* h, const double* xyz, int64_t n_vert, const int32_t* tri, int64_t n_tri,
+                          const int32_t* obj, int32_t n_obj) {
+  return guard(h, [&]() {
+    SLIM_REQUIRE(xyz && tri && obj && n_vert > 0 && n_tri > 0 && n_obj > 0, SLIM_E_ARG, "null or empty mesh arrays");
+    SLIM_REQUIRE(n_tri < (int64_t(1) << 31) && n_vert < (int64_t(1) << 31), SLIM_E_ARG, "mesh too large for int32 ids");
+    Mesh m;
+    m.n_vert = n_vert;
+    m.n_tri = n_tri;
+    m.n_obj = n_obj;
+    m.xyz.assign(xyz, xyz + 3 * n_vert);
+    m.tri.assign(tri, tri + 3 * n_tri);
+    m.obj.assign(obj, obj + n_tri);
+    for (double v : m.xyz) SLIM_REQUIRE(std::isfinite(v), SLIM_E_MESH, "non-finite vertex coordinate");
+    RWGTable r = build_rwg(m);   // throws SLIM_E_MESH and leaves the context unchanged
+    h->c.mesh = std::move(m);
+    h->c.rwg = std::move(r);
+    h->c.has_mesh = true;
+    h->c.built = false;
+    h->c.mats.clear();
+    return SLIM_OK;
+  });
+}
+
+slim_status slim_set_materials(slim_ctx* h, const slim_material* per_obj) {
+  return guard(h, [&]() {
+    SLIM_REQUIRE(h->c.has_mesh, SLIM_E_STATE, "slim_set_mesh must come first");
+    std::vector<Material> mats(h->c.mesh.n_obj);
+    if (per_obj)
+      for (int i = 0; i < h->c.mesh.n_obj; ++i) {
+        SLIM_REQUIRE(per_obj[i].sigma >= 0 && per_obj[i].eps_r > 0 && per_obj[i].mu_r > 0, SLIM_E_ARG,
+                     "invalid material of object " + std::to_string(i));
+        mats[i] = {per_obj[i].sigma, per_obj[i].eps_r, per_obj[i].mu_r};
+      }
+    h->c.mats = std::move(mats);
+    h->c.built = false;
+    return SLIM_OK;
+  });
+}
+
+slim_status slim_build(slim_ctx* h, const slim_build_opts* o) {
+  return guard(h, [&]() {
+    SLIM_REQUIRE(o, SLIM_E_ARG, "null build options");
+    try {
+      build_all(h->c, *o);
+    } catch (...) {
+      h->c.built = false;
+      throw;
+    }
+    return SLIM_OK;
+  });
+}
+
+slim_status slim_get_layout(const slim_ctx* h, slim_layout* out) {
+  if (!h || !out) return SLIM_E_ARG;
+  if (!h->c.built) return SLIM_E_STATE;
+  *out = h->c.layout;
+  return SLIM_OK;
+}
+
+slim_status slim_get_rwg(const slim_ctx* h, int32_t* ev, int32_t* tp, int32_t* tm) {
+  if (!h) return SLIM_E_ARG;
+  if (!h->c.has_mesh) return SLIM_E_STATE;
+  const RWGTable& r = h->c.rwg;
+  if (ev) std::copy(r.ev.begin(), r.ev.end(), ev);
+  if (tp) std::copy(r.tplus.begin(), r.tplus.end(), tp);
+  if (tm) std::copy(r.tminus.begin(), r.tminus.end(), tm);
+  return SLIM_OK;
+}
+
+slim_status slim_matvec(slim_ctx* h, slim_prec prec, const void* x, void* y, void* stream) {
+  return slim_matvec_parts(h, prec, x, y, nullptr, nullptr, nullptr, nullptr, stream);
+}
+
+slim_status slim_matvec_parts(slim_ctx* h, slim_prec prec, const void* x, void* y, void* e, void* g, void* a, void* phi,
+                              void* stream) {
+  return guard(h, [&]() {
+    SLIM_REQUIRE(h->c.built, SLIM_E_STATE, "operator not built");
+    SLIM_REQUIRE(x && y && x != y, SLIM_E_ARG, "x and y must be distinct device buffers");
+    SLIM_REQUIRE(prec == SLIM_FP64 || prec == SLIM_MIXED, SLIM_E_ARG, "unknown precision");
+    SLIM_HIP(hipSetDevice(h->c.device));
+    matvec(h->c, prec, x, y, e, g, a, phi, as_stream(stream));
+    return SLIM_OK;
+  });
+}
+
+slim_status slim_internal_apply(slim_ctx* h, slim_prec prec, const void* H, void* e, void* g, double* ms, void* stream) {
+  return guard(h, [&]() {
+    SLIM_REQUIRE(h->c.built, SLIM_E_STATE, "operator not built");
+    SLIM_REQUIRE(H, SLIM_E_ARG, "null H");
+    SLIM_HIP(hipSetDevice(h->c.device));
+    hipStream_t s = as_stream(stream);
+    if (ms) {
+      hipEvent_t a, b;
+      SLIM_HIP(hipEventCreate(&a));
+      SLIM_HIP(hipEventCreate(&b));
+      if (prec != SLIM_FP64) launch_cast_c128_to_c64(H, h->c.d_x64.p, h->c.rwg.n_e, s);
+      SLIM_HIP(hipEventRecord(a, s));
+      internal_apply(h->c, prec, H, e, g, s, true);
+      SLIM_HIP(hipEventRecord(b, s));
+      SLIM_HIP(hipEventSynchronize(b));
+      float t = 0.f;
+      SLIM_HIP(hipEventElapsedTime(&t, a, b));
+      *ms = t;
+      (void)hipEventDestroy(a);
+      (void)hipEventDestroy(b);
+      if (h->c.record) {
+        h->c.last_stamps.resize(2 * h->c.tiles.size());
+        std::vector<unsigned long long> st(2 * h->c.tiles.size());
+        SLIM_HIP(hipMemcpy(st.data(), h->c.d_stamps.p, st.size() * 8, hipMemcpyDeviceToHost));
+        for (size_t k = 0; k < st.size(); ++k) h->c.last_stamps[k] = double(st[k]);
+      }
+    } else {
+      internal_apply(h->c, prec, H, e, g, s, true);
+    }
+    return SLIM_OK;
+  });
+}
+
+slim_status slim_rhs_planewave(slim_ctx* h, const double khat[3], const double epol[3], void* b, void* stream) {
+  return guard(h, [&]() {
+    SLIM_REQUIRE(h->c.built, SLIM_E_STATE, "operator not built");
+    SLIM_REQUIRE(khat && epol && b, SLIM_E_ARG, "null argument");
+    // b1[m] = (1/eta0) int f_m . epol e^{-j k0 khat.r} dS with TRI(4); b2 = 0
+    const RWGTable& r = h->c.rwg;
+    const Mesh& m = h->c.mesh;
+    std::vector<cd> out(r.n_e + r.n_t, cd(0.0));
+    std::vector<double> gx = {0.06943184420297371, 0.33000947820757187, 0.6699905217924281, 0.9305681557970262};
+    std::vector<double> gw = {0.17392742256872692, 0.3260725774312731, 0.3260725774312731, 0.17392742256872692};
+    for (int64_t t = 0; t < r.n_t; ++t) {
+      const double* v0 = &m.xyz[3 * size_t(m.tri[3 * t])];
+      const double* v1 = &m.xyz[3 * size_t(m.tri[3 * t + 1])];
+      const double* v2 = &m.xyz[3 * size_t(m.tri[3 * t + 2])];
+      for (int a = 0; a < 4; ++a)
+        for (int bq = 0; bq < 4; ++bq) {
+          double u = gx[a], v = gx[bq] * (1 - gx[a]), w = 2 * r.area[t] * gw[a] * gw[bq] * (1 - gx[a]);
+          double p[3];
+          for (int k = 0; k < 3; ++k) p[k] = v0[k] + u * (v1[k] - v0[k]) + v * (v2[k] - v0[k]);
+          cd ph = std::exp(cd(0.0, -h->c.k0 * (khat[0] * p[0] + khat[1] * p[1] + khat[2] * p[2])));
+          for (int i = 0; i < 3; ++i) {
+            const int n = r.tri_edge[3 * t + i];
+            const double* pv = &m.xyz[3 * size_t(m.tri[3 * t + i])];
+            double cf = r.tri_sign[3 * t + i] * r.len[n] / (2 * r.area[t]);
+            double fe = 0.0;
+            for (int k = 0; k < 3; ++k) fe += cf * (p[k] - pv[k]) * epol[k];
+            out[n] += w * fe * ph / eta0();
+          }
+        }
+    }
+    SLIM_HIP(hipMemcpyAsync(b, out.data(), out.size() * 16, hipMemcpyHostToDevice, as_stream(stream)));
+    SLIM_HIP(hipStreamSynchronize(as_stream(stream)));
+    return SLIM_OK;
+  });
+}
+
+slim_status slim_solve(slim_ctx* h, const void* b, int32_t scaled_rhs, void* x, const slim_solve_opts* o,
+                       slim_solve_info* info, void* stream) {
+  return guard(h, [&]() {
+    SLIM_REQUIRE(h->c.built, SLIM_E_STATE, "operator not built");
+    SLIM_REQUIRE(b && x && o && b != x, SLIM_E_ARG, "null or aliased argument");
+    SLIM_HIP(hipSetDevice(h->c.device));
+    slim_solve_info tmp{};
+    slim_status st = solve_gmres(h->c, b, scaled_rhs, x, *o, tmp, as_stream(stream));
+    if (info) *info = tmp;
+    if (st == SLIM_E_NOT_CONVERGED) h->c.last_error = "GMRES did not reach the tolerance";
+    return st;
+  });
+}
+
+slim_status slim_sched_record(slim_ctx* h, int32_t on) {
+  return guard(h, [&]() {
+    h->c.record = on != 0;
+    return SLIM_OK;
+  });
+}
+
+slim_status slim_sched_tiles(slim_ctx* h, double* out, int64_t* n_tiles) {
+  return guard(h, [&]() {
+    SLIM_REQUIRE(n_tiles, SLIM_E_ARG, "null count");
+    SLIM_REQUIRE(h->c.built, SLIM_E_STATE, "operator not built");
+    const int64_t n = int64_t(h->c.tiles.size());
+    const int64_t cap = *n_tiles;
+    *n_tiles = n;
+    if (!out) return SLIM_OK;
+    SLIM_REQUIRE(cap >= n, SLIM_E_ARG, "tile buffer too small");
+    for (int64_t k = 0; k < n; ++k) {
+      const Tile& t = h->c.tiles[k];
+      out[7 * k] = t.block;
+      out[7 * k + 1] = t.row0;
+      out[7 * k + 2] = t.rows;
+      out[7 * k + 3] = h->c.blocks[t.block].n;
+      out[7 * k + 4] = t.slot;
+      const bool have = int64_t(h->c.last_stamps.size()) == 2 * n;
+      out[7 * k + 5] = have ? h->c.last_stamps[2 * k] : 0.0;
+      out[7 * k + 6] = have ? h->c.last_stamps[2 * k + 1] : 0.0;
+    }
+    return SLIM_OK;
+  });
+}
+
+slim_status slim_sched_set_mode(slim_ctx* h, int32_t mode) {
+  return guard(h, [&]() {
+    SLIM_REQUIRE(h->c.built, SLIM_E_STATE, "operator not built");
+    SLIM_REQUIRE(mode >= 0 && mode <= 2, SLIM_E_ARG, "unknown scheduling mode");
+    SLIM_REQUIRE(mode != 1 || !h->c.mlp_params.empty(), SLIM_E_STATE, "cost model not trained");
+    pack_tiles(h->c, mode);
+    h->c.last_stamps.clear();
+    h->c.layout.n_tiles = int64_t(h->c.tiles.size());
+    return SLIM_OK;
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,136 @@
+// The library context: host tables and device arenas of one built operator.
+#pragma once
+#include <memory>
+
+#include "common.hpp"
+#include "quad.hpp"
+
+namespace slim {
+
+// AIM grid (eq. (11)): N nodes per axis, spacing h, origin; FFT size 2N.
+struct GridDef {
+  int N[3] = {0, 0, 0};
+  double h[3] = {0, 0, 0};
+  double origin[3] = {0, 0, 0};
+  int64_t nodes() const { return int64_t(N[0]) * N[1] * N[2]; }
+};
+
+// One internal work tile: rows [row0, row0+rows) of the stacked [Z_i; M_i] block.
+struct Tile {
+  int32_t block, row0, rows, slot;
+};
+
+struct Block {
+  int64_t off;   // element offset of the 2n x n row-major block in the arena
+  int32_t n;     // unknowns of the object
+  int32_t e0;    // first global RWG index
+};
+
+template <class T> struct Cplx { T x, y; };
+
+struct Ctx {
+  int device = 0;
+  std::string last_error;
+  bool has_mesh = false, built = false;
+  Mesh mesh;
+  std::vector<Material> mats;
+  RWGTable rwg;
+  slim_build_opts opts{};
+  slim_layout layout{};
+  double freq = 0, omega = 0, k0 = 0;
+  cd eps_c_obj;                         // (homogeneous materials: per object below)
+  std::vector<cd> kc, epsc;             // per object
+
+  // ---- geometry on the device (build and combine) ----
+  DevBuf d_xyz, d_tri, d_cen, d_nrm, d_area, d_diam, d_tri_edge, d_tri_sign, d_len, d_tplus, d_tminus;
+
+  // ---- internal arena (rows of [Z_i; M_i], row-major, hi and lo complex64) ----
+  std::vector<Block> blocks;
+  DevBuf d_hi, d_lo;                    // Cplx<float>
+  DevBuf d_blocks;                      // Block[]
+  int64_t arena_elems = 0;
+
+  // ---- work queues of the persistent internal kernel ----
+  std::vector<Tile> tiles;              // grouped by slot
+  std::vector<int32_t> slot_start;      // slots+1
+  DevBuf d_tiles, d_slot_start;
+  int slots = 0;
+  int tile_rows = 64;
+  int sched_mode = 0;
+  bool record = false;
+  DevBuf d_stamps;                      // 2 x n_tiles uint64 timestamps
+  std::vector<double> last_stamps;
+
+  // ---- I_x (sparse: the other edges of T+ and T-), per RWG row ----
+  DevBuf d_ix_col;                      // 4 n_e int32 (-1 if unused)
+  DevBuf d_ix_val;                      // 4 n_e double
+
+  // ---- external: dense (plain mode) ----
+  bool plain = false;
+  DevBuf d_LA_hi, d_LA_lo, d_Lphi_hi, d_Lphi_lo;   // row-major, hi / lo complex64
+
+  // ---- external: AIM ----
+  GridDef grid;
+  int near_cheb = 3;
+  // projection P (grid-node-major, atomic-free gather)
+  DevBuf d_pe_node, d_pe_ptr, d_pe_idx, d_pe_w32, d_pe_w64;   // RWG: (node list, row ptr, basis, 3 weights)
+  DevBuf d_pt_node, d_pt_ptr, d_pt_idx, d_pt_w32, d_pt_w64;   // pulses (weights x A_t)
+  int64_t n_pe_nodes = 0, n_pt_nodes = 0, nnz_pe = 0, nnz_pt = 0;
+  // interpolation W = P^T (basis-major: base node + 27 weights per component)
+  DevBuf d_we_base, d_we_w32, d_we_w64, d_wt_base, d_wt_w32, d_wt_w64;
+  // Green's function spectrum on the (2N)^3 grid, scaled by 1/(2N)^3
+  DevBuf d_ghat64, d_ghat128;
+  DevBuf d_tw64, d_tw128;               // twiddles for each axis length
+  // FFT work arrays (4 components)
+  DevBuf d_oct_in, d_oct_in32;          // projected sources: complex128 / complex64 (zero off the occupied nodes)
+  DevBuf d_oct_out, d_x1, d_x2;         // sized for complex128; complex64 uses the front
+  // near field
+  DevBuf d_nA_ptr, d_nA_col, d_nA_v128, d_nA_v64;
+  DevBuf d_nP_ptr, d_nP_col, d_nP_v128, d_nP_v64;     // columns pre-scaled by A_u
+  int64_t nnz_A = 0, nnz_P = 0;
+
+  // ---- vectors ----
+  DevBuf d_x64, d_y64;                  // complex64 copies of x / scratch
+  DevBuf d_e, d_g, d_j, d_a, d_phi;     // sized for complex128
+
+  // ---- graphs ----
+  hipStream_t s_aux = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+
+  // ---- cost model ----
+  std::vector<float> mlp_params;        // trained FP32 parameters (empty: untrained)
+  std::vector<float> mlp_mu, mlp_sd;    // feature standardisation
+
+  ~Ctx();
+};
+
+// build.cpp
+void build_all(Ctx& c, const slim_build_opts& o);
+// aim.cpp
+void build_aim(Ctx& c, hipStream_t s);
+// kernels.hip
+void matvec(Ctx& c, slim_prec prec, const void* x, void* y, void* e_out, void* g_out, void* a_out,
+            void* phi_out, hipStream_t s);
+void internal_apply(Ctx& c, slim_prec prec, const void* H, void* e, void* g, hipStream_t s, bool h_is_c128);
+void launch_cast_c128_to_c64(const void* in, void* out, int64_t n, hipStream_t s);
+void launch_cast_c64_to_c128(const void* in, void* out, int64_t n, hipStream_t s);
+void launch_pack_block(const double* Zcm, const double* Mcm, int n, Cplx<float>* hi, Cplx<float>* lo, hipStream_t s);
+void launch_add_scaled_ix(double* B, const int32_t* ix_col, const double* ix_val, int e0, int n, double half, hipStream_t s);
+void launch_scale(double* M, int64_t n_elems, cd f, hipStream_t s);
+void launch_usolve_block(const double* U, int64_t ld, int i0, int nb, double* X, int64_t ldx, int nrhs, hipStream_t s);
+void launch_pack_dense(const double* Acm, int64_t rows, int64_t cols, Cplx<float>* hi, Cplx<float>* lo, hipStream_t s);
+// fft.hip
+void fft_init_twiddles(Ctx& c);
+void fft_forward_3d_c128(Ctx& c, double* data_full, hipStream_t s);   // full (2N)^3 in place (build)
+void aim_convolve(Ctx& c, bool fp64, int ncomp, hipStream_t s);        // oct_in -> oct_out, ncomp components
+// sched.cpp
+void pack_tiles(Ctx& c, int mode);
+// solve.cpp
+slim_status solve_gmres(Ctx& c, const void* b, int scaled_rhs, void* x, const slim_solve_opts& o,
+                        slim_solve_info& info, hipStream_t s);
+
+}  // namespace slim
+
+struct slim_ctx {
+  slim::Ctx c;
+};

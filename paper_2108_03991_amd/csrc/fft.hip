@@ -1,0 +1,299 @@
+// Grid convolution H of eq. (11) by FFT on the zero-padded (2N)^3 grid.
+//
+// One pass transforms every line along one axis.  A workgroup stages a batch of
+// lines in LDS (8192 complex64 or 4096 complex128 elements), runs a Stockham
+// autosort FFT with radix-8/4/2 butterflies held in registers, and writes the
+// result back.  Passes of the convolution, per component (x, y, z, rho):
+//   x-fwd  (reads the N^3 octant, the upper half of each line is zero)
+//   y-fwd  (upper half zero)
+//   z      (upper half zero; forward, times the spectrum G^, inverse; only the
+//           lower half of the result is kept)
+//   y-inv  (keeps the lower half)   x-inv (keeps the lower half -> octant)
+// so 26 N^3 elements move per component instead of the 48 N^3 of unpruned
+// passes with a separate spectrum multiply.
+#include "ctx.hpp"
+
+namespace slim {
+
+namespace {
+
+template <class T> struct C2 { T x, y; };
+template <class T> __device__ __forceinline__ C2<T> cadd(C2<T> a, C2<T> b) { return {a.x + b.x, a.y + b.y}; }
+template <class T> __device__ __forceinline__ C2<T> csub(C2<T> a, C2<T> b) { return {a.x - b.x, a.y - b.y}; }
+template <class T> __device__ __forceinline__ C2<T> cmul(C2<T> a, C2<T> b) {
+  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+// multiply by -i (forward) or +i (inverse)
+template <class T, bool INV> __device__ __forceinline__ C2<T> rot90(C2<T> a) {
+  return INV ? C2<T>{-a.y, a.x} : C2<T>{a.y, -a.x};
+}
+
+template <class T, bool INV> __device__ __forceinline__ void dft2(C2<T>* v) {
+  C2<T> a = v[0], b = v[1];
+  v[0] = cadd(a, b);
+  v[1] = csub(a, b);
+}
+
+template <class T, bool INV> __device__ __forceinline__ void dft4(C2<T>* v) {
+  C2<T> t0 = cadd(v[0], v[2]), t1 = csub(v[0], v[2]);
+  C2<T> t2 = cadd(v[1], v[3]), t3 = rot90<T, INV>(csub(v[1], v[3]));
+  v[0] = cadd(t0, t2);
+  v[2] = csub(t0, t2);
+  v[1] = cadd(t1, t3);
+  v[3] = csub(t1, t3);
+}
+
+template <class T, bool INV> __device__ __forceinline__ void dft8(C2<T>* v) {
+  C2<T> e[4] = {v[0], v[2], v[4], v[6]}, o[4] = {v[1], v[3], v[5], v[7]};
+  dft4<T, INV>(e);
+  dft4<T, INV>(o);
+  const T r = T(0.70710678118654752440);
+  // w8^k for k = 0..3, w8 = e^{-i pi/4} (forward) or e^{+i pi/4} (inverse)
+  C2<T> w1 = INV ? C2<T>{r, r} : C2<T>{r, -r};
+  C2<T> w3 = INV ? C2<T>{-r, r} : C2<T>{-r, -r};
+  C2<T> o1 = cmul(o[1], w1), o2 = rot90<T, INV>(o[2]), o3 = cmul(o[3], w3);
+  v[0] = cadd(e[0], o[0]); v[4] = csub(e[0], o[0]);
+  v[1] = cadd(e[1], o1);   v[5] = csub(e[1], o1);
+  v[2] = cadd(e[2], o2);   v[6] = csub(e[2], o2);
+  v[3] = cadd(e[3], o3);   v[7] = csub(e[3], o3);
+}
+
+template <int R, class T, bool INV> __device__ __forceinline__ void dftR(C2<T>* v) {
+  if constexpr (R == 8) dft8<T, INV>(v);
+  else if constexpr (R == 4) dft4<T, INV>(v);
+  else dft2<T, INV>(v);
+}
+
+// One Stockham stage of radix R on every line of the LDS batch (in place through registers).
+// Element j + r L/R of the input feeds output (j/Ns) Ns R + j%Ns + r Ns, after the
+// twiddle e^{-+2 pi i (j%Ns) r / (Ns R)} and an R-point DFT.
+template <class T, int L, int R, int ELEMS, bool INV>
+__device__ __forceinline__ void stage(C2<T>* lds, int Ns, const C2<T>* tw) {
+  constexpr int NB = ELEMS / R;           // butterflies in the batch
+  constexpr int PER = NB / 256;           // per thread
+  static_assert(NB % 256 == 0, "batch too small");
+  C2<T> v[PER][R];
+  int outb[PER];
+#pragma unroll
+  for (int p = 0; p < PER; ++p) {
+    const int it = threadIdx.x + p * 256;
+    const int line = it / (L / R), j = it % (L / R);
+    C2<T>* base = lds + line * L;
+    const int k = j % Ns;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      C2<T> x = base[j + r * (L / R)];
+      if (r > 0 && Ns > 1) {
+        // twiddle index k r L/(Ns R) in [0, L)
+        C2<T> w = tw[(k * r * (L / (Ns * R))) % L];
+        if (INV) w.y = -w.y;
+        x = cmul(x, w);
+      }
+      v[p][r] = x;
+    }
+    dftR<R, T, INV>(v[p]);
+    outb[p] = line * L + (j / Ns) * Ns * R + k;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int p = 0; p < PER; ++p)
+#pragma unroll
+    for (int r = 0; r < R; ++r) lds[outb[p] + r * Ns] = v[p][r];
+  __syncthreads();
+}
+
+template <class T, int L, int ELEMS, bool INV>
+__device__ void fft_batch(C2<T>* lds, const C2<T>* tw) {
+  int Ns = 1;
+  int rem = L;
+  while (rem >= 8) { stage<T, L, 8, ELEMS, INV>(lds, Ns, tw); Ns *= 8; rem /= 8; }
+  if (rem == 4) { stage<T, L, 4, ELEMS, INV>(lds, Ns, tw); Ns *= 4; rem /= 4; }
+  if (rem == 2) { stage<T, L, 2, ELEMS, INV>(lds, Ns, tw); }
+}
+
+struct PassArgs {
+  const void* in; void* out;
+  int64_t in_e, in_o1, in_o2, out_e, out_o1, out_o2;
+  int n1, n2;            // line counts along the two outer indices
+  int n_in, n_out;       // elements read (others zero) / written per line
+  const void* tw;        // L twiddles e^{-2 pi i m / L}
+  const void* mul;       // spectrum for the fused pass
+  int64_t mul_e, mul_o1, mul_o2;
+  int64_t comp_in, comp_out;   // component strides (blockIdx.z)
+};
+
+// MODE 0: forward, 1: inverse, 2: forward, multiply, inverse.
+// CONTIG: lines are contiguous (in_e == 1), batch = consecutive lines along o1;
+// otherwise the batch is W = ELEMS/L adjacent lines (o1 stride 1) for coalescing.
+template <class T, int L, bool CONTIG, int MODE>
+__global__ void __launch_bounds__(256) k_fft_pass(PassArgs a) {
+  constexpr int ELEMS = sizeof(T) == 4 ? 8192 : 4096;
+  constexpr int W = ELEMS / L;
+  extern __shared__ unsigned char smem_raw[];
+  C2<T>* lds = reinterpret_cast<C2<T>*>(smem_raw);
+  const C2<T>* tw = reinterpret_cast<const C2<T>*>(a.tw);
+  const C2<T>* in = reinterpret_cast<const C2<T>*>(a.in) + blockIdx.z * a.comp_in;
+  C2<T>* out = reinterpret_cast<C2<T>*>(a.out) + blockIdx.z * a.comp_out;
+  const int g1 = blockIdx.x * W;     // first line along o1
+  const int o2 = blockIdx.y;
+  // load
+  for (int e = threadIdx.x; e < ELEMS; e += 256) {
+    int b, i;
+    if (CONTIG) { b = e / L; i = e % L; } else { b = e % W; i = e / W; }
+    const int o1 = g1 + b;
+    C2<T> v = {T(0), T(0)};
+    if (o1 < a.n1 && i < a.n_in) v = in[o1 * a.in_o1 + o2 * a.in_o2 + int64_t(i) * a.in_e];
+    lds[b * L + i] = v;
+  }
+  __syncthreads();
+  if (MODE == 1) fft_batch<T, L, ELEMS, true>(lds, tw);
+  else fft_batch<T, L, ELEMS, false>(lds, tw);
+  if (MODE == 2) {
+    const C2<T>* G = reinterpret_cast<const C2<T>*>(a.mul);
+    for (int e = threadIdx.x; e < ELEMS; e += 256) {
+      int b, i;
+      if (CONTIG) { b = e / L; i = e % L; } else { b = e % W; i = e / W; }
+      const int o1 = g1 + b;
+      if (o1 < a.n1) lds[b * L + i] = cmul(lds[b * L + i], G[o1 * a.mul_o1 + o2 * a.mul_o2 + int64_t(i) * a.mul_e]);
+    }
+    __syncthreads();
+    fft_batch<T, L, ELEMS, true>(lds, tw);
+  }
+  for (int e = threadIdx.x; e < ELEMS; e += 256) {
+    int b, i;
+    if (CONTIG) { b = e / L; i = e % L; } else { b = e % W; i = e / W; }
+    const int o1 = g1 + b;
+    if (o1 < a.n1 && i < a.n_out) out[o1 * a.out_o1 + o2 * a.out_o2 + int64_t(i) * a.out_e] = lds[b * L + i];
+  }
+}
+
+template <class T, bool CONTIG, int MODE>
+void launch_pass_L(int L, const PassArgs& a, int ncomp, hipStream_t s) {
+  constexpr int ELEMS = sizeof(T) == 4 ? 8192 : 4096;
+  const size_t shm = size_t(ELEMS) * sizeof(C2<T>);
+  const int W = ELEMS / L;
+  dim3 grid(unsigned((a.n1 + W - 1) / W), unsigned(a.n2), unsigned(ncomp));
+  switch (L) {
+#define SLIM_FFT_CASE(LL)                                                                          \
+  case LL: hipLaunchKernelGGL((k_fft_pass<T, LL, CONTIG, MODE>), grid, dim3(256), shm, s, a); break;
+    SLIM_FFT_CASE(16) SLIM_FFT_CASE(32) SLIM_FFT_CASE(64) SLIM_FFT_CASE(128) SLIM_FFT_CASE(256)
+    SLIM_FFT_CASE(512) SLIM_FFT_CASE(1024)
+#undef SLIM_FFT_CASE
+    default: throw Error(SLIM_E_UNSUPPORTED, "FFT length " + std::to_string(L) + " (2N must be a power of two in [16, 1024])");
+  }
+  SLIM_HIP(hipGetLastError());
+}
+
+}  // namespace
+
+void fft_init_twiddles(Ctx& c) {
+  // three tables (one per axis), each of length 2 N_c
+  std::vector<double> t128;
+  std::vector<float> t64;
+  for (int ax = 0; ax < 3; ++ax) {
+    const int L = 2 * c.grid.N[ax];
+    SLIM_REQUIRE(L >= 16 && L <= 1024 && (L & (L - 1)) == 0, SLIM_E_UNSUPPORTED,
+                 "AIM grid size must be a power of two between 8 and 512 per axis");
+    for (int m = 0; m < L; ++m) {
+      double ang = -2.0 * kPi * double(m) / double(L);
+      t128.push_back(std::cos(ang));
+      t128.push_back(std::sin(ang));
+      t64.push_back(float(std::cos(ang)));
+      t64.push_back(float(std::sin(ang)));
+    }
+  }
+  c.d_tw128.upload(t128);
+  c.d_tw64.upload(t64);
+}
+
+static size_t tw_off(const Ctx& c, int ax) {
+  size_t o = 0;
+  for (int k = 0; k < ax; ++k) o += size_t(2 * c.grid.N[k]);
+  return o;
+}
+
+void fft_forward_3d_c128(Ctx& c, double* data, hipStream_t s) {
+  const int X2 = 2 * c.grid.N[0], Y2 = 2 * c.grid.N[1], Z2 = 2 * c.grid.N[2];
+  const C2<double>* tw = c.d_tw128.as<C2<double>>();
+  PassArgs a{};
+  a.in = data; a.out = data; a.comp_in = a.comp_out = 0;
+  // x: lines (y, z), contiguous
+  a.in_e = a.out_e = 1; a.in_o1 = a.out_o1 = X2; a.in_o2 = a.out_o2 = int64_t(X2) * Y2;
+  a.n1 = Y2; a.n2 = Z2; a.n_in = a.n_out = X2; a.tw = tw + tw_off(c, 0);
+  launch_pass_L<double, true, 0>(X2, a, 1, s);
+  // y: lines (x, z), stride X2
+  a.in_e = a.out_e = X2; a.in_o1 = a.out_o1 = 1; a.in_o2 = a.out_o2 = int64_t(X2) * Y2;
+  a.n1 = X2; a.n2 = Z2; a.n_in = a.n_out = Y2; a.tw = tw + tw_off(c, 1);
+  launch_pass_L<double, false, 0>(Y2, a, 1, s);
+  // z: lines (x, y), stride X2 Y2
+  a.in_e = a.out_e = int64_t(X2) * Y2; a.in_o1 = a.out_o1 = 1; a.in_o2 = a.out_o2 = X2;
+  a.n1 = X2; a.n2 = Y2; a.n_in = a.n_out = Z2; a.tw = tw + tw_off(c, 2);
+  launch_pass_L<double, false, 0>(Z2, a, 1, s);
+}
+
+// oct_in (ncomp x N^3, [z][y][x]) -> oct_out, each convolved with the grid Green's function.
+void aim_convolve(Ctx& c, bool fp64, int ncomp, hipStream_t s) {
+  const int Nx = c.grid.N[0], Ny = c.grid.N[1], Nz = c.grid.N[2];
+  const int X2 = 2 * Nx, Y2 = 2 * Ny, Z2 = 2 * Nz;
+  const int64_t N3 = c.grid.nodes();
+  const size_t esz = fp64 ? 16 : 8;
+  char* oin = reinterpret_cast<char*>(fp64 ? c.d_oct_in.p : c.d_oct_in32.p);
+  char* oout = reinterpret_cast<char*>(c.d_oct_out.p);
+  char* x1 = reinterpret_cast<char*>(c.d_x1.p);
+  char* x2 = reinterpret_cast<char*>(c.d_x2.p);
+  (void)esz;
+  auto run = [&](auto tag) {
+    using T = decltype(tag);
+    const C2<T>* tw = reinterpret_cast<const C2<T>*>(fp64 ? c.d_tw128.p : c.d_tw64.p);
+    PassArgs a{};
+    // x-fwd: octant [Nz][Ny][Nx] -> X1 [Nz][Ny][X2]
+    a.in = oin; a.out = x1;
+    a.in_e = 1; a.in_o1 = Nx; a.in_o2 = int64_t(Nx) * Ny;
+    a.out_e = 1; a.out_o1 = X2; a.out_o2 = int64_t(X2) * Ny;
+    a.n1 = Ny; a.n2 = Nz; a.n_in = Nx; a.n_out = X2;
+    a.comp_in = N3; a.comp_out = 2 * N3;
+    a.tw = tw + tw_off(c, 0);
+    launch_pass_L<T, true, 0>(X2, a, ncomp, s);
+    // y-fwd: X1 [Nz][Ny][X2] -> X2 [Nz][Y2][X2]
+    a = PassArgs{};
+    a.in = x1; a.out = x2;
+    a.in_e = X2; a.in_o1 = 1; a.in_o2 = int64_t(X2) * Ny;
+    a.out_e = X2; a.out_o1 = 1; a.out_o2 = int64_t(X2) * Y2;
+    a.n1 = X2; a.n2 = Nz; a.n_in = Ny; a.n_out = Y2;
+    a.comp_in = 2 * N3; a.comp_out = 4 * N3;
+    a.tw = tw + tw_off(c, 1);
+    launch_pass_L<T, false, 0>(Y2, a, ncomp, s);
+    // z fused: X2 lines (kx, ky), stride X2 Y2; forward, x G^, inverse, keep z < Nz
+    a = PassArgs{};
+    a.in = x2; a.out = x2;
+    a.in_e = a.out_e = int64_t(X2) * Y2; a.in_o1 = a.out_o1 = 1; a.in_o2 = a.out_o2 = X2;
+    a.n1 = X2; a.n2 = Y2; a.n_in = Nz; a.n_out = Nz;
+    a.mul = fp64 ? c.d_ghat128.p : c.d_ghat64.p;
+    a.mul_e = int64_t(X2) * Y2; a.mul_o1 = 1; a.mul_o2 = X2;
+    a.comp_in = a.comp_out = 4 * N3;
+    a.tw = tw + tw_off(c, 2);
+    launch_pass_L<T, false, 2>(Z2, a, ncomp, s);
+    // y-inv: X2 [Nz][Y2][X2] -> X1 [Nz][Ny][X2] (keep y < Ny)
+    a = PassArgs{};
+    a.in = x2; a.out = x1;
+    a.in_e = X2; a.in_o1 = 1; a.in_o2 = int64_t(X2) * Y2;
+    a.out_e = X2; a.out_o1 = 1; a.out_o2 = int64_t(X2) * Ny;
+    a.n1 = X2; a.n2 = Nz; a.n_in = Y2; a.n_out = Ny;
+    a.comp_in = 4 * N3; a.comp_out = 2 * N3;
+    a.tw = tw + tw_off(c, 1);
+    launch_pass_L<T, false, 1>(Y2, a, ncomp, s);
+    // x-inv: X1 [Nz][Ny][X2] -> octant (keep x < Nx)
+    a = PassArgs{};
+    a.in = x1; a.out = oout;
+    a.in_e = 1; a.in_o1 = X2; a.in_o2 = int64_t(X2) * Ny;
+    a.out_e = 1; a.out_o1 = Nx; a.out_o2 = int64_t(Nx) * Ny;
+    a.n1 = Ny; a.n2 = Nz; a.n_in = X2; a.n_out = Nx;
+    a.comp_in = 2 * N3; a.comp_out = N3;
+    a.tw = tw + tw_off(c, 0);
+    launch_pass_L<T, true, 1>(X2, a, ncomp, s);
+  };
+  if (fp64) run(double{});
+  else run(float{});
+}
+
+}  // namespace slim

@@ -1,0 +1,530 @@
+// Kernels of the system matrix-vector product (eq. (7)-(8)) and its driver.
+//
+//   e = Z H,  g = M H (M = Y_eq Z, eq. (6)),  j = H - g (eq. (2)),  q = B c0rho
+//   a = L_A j,  phi = L_phi q   (AIM, eq. (11): L_NR + W H P; or dense)
+//   y1 = j k0 a + D^T phi + I_x e / eta0,   y2 = F D j + j k0 c0rho
+//
+// Precision: FP64 (internal blocks as hi + lo complex64, everything else
+// complex128) or MIXED (hi complex64 blocks, FP32 accumulation, complex64 FFT,
+// near field and vectors).  The ABI vectors are always complex128.
+#include "ctx.hpp"
+
+namespace slim {
+
+namespace {
+
+template <class T> struct C2 { T x, y; };
+template <class T> __device__ __forceinline__ C2<T> cz() { return {T(0), T(0)}; }
+
+template <bool F64> struct P;
+template <> struct P<true> { using T = double; };
+template <> struct P<false> { using T = float; };
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+unsigned nblk(int64_t n, int t = 256) { return unsigned((n + t - 1) / t); }
+
+// ---------------------------------------------------------------------------
+// Casts
+// ---------------------------------------------------------------------------
+__global__ void k_c128_to_c64(const double2* in, float2* out, int64_t n) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = make_float2(float(in[i].x), float(in[i].y));
+}
+__global__ void k_c64_to_c128(const float2* in, double2* out, int64_t n) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = make_double2(double(in[i].x), double(in[i].y));
+}
+
+// ---------------------------------------------------------------------------
+// Build helpers
+// ---------------------------------------------------------------------------
+// Column-major complex128 Z and M (n x n) -> rows of the stacked row-major block
+// [Z; M] with leading dimension ld, split into hi = fl32(v), lo = fl32(v - hi).
+__global__ void k_pack_block(const double2* Z, const double2* M, int n, int ld, float2* hi, float2* lo) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t tot = int64_t(2 * n) * ld;
+  if (i >= tot) return;
+  const int row = int(i / ld), col = int(i % ld);
+  double2 v = make_double2(0.0, 0.0);
+  if (col < n) v = row < n ? Z[row + int64_t(col) * n] : M[(row - n) + int64_t(col) * n];
+  float2 h = make_float2(float(v.x), float(v.y));
+  hi[i] = h;
+  lo[i] = make_float2(float(v.x - double(h.x)), float(v.y - double(h.y)));
+}
+
+__global__ void k_pack_dense(const double2* A, int64_t n, float2* hi, float2* lo) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double2 v = A[i];
+  float2 h = make_float2(float(v.x), float(v.y));
+  hi[i] = h;
+  lo[i] = make_float2(float(v.x - double(h.x)), float(v.y - double(h.y)));
+}
+
+// B (column-major n x n, local RWG indices) += half * I_x
+__global__ void k_add_ix(double2* B, const int32_t* col, const double* val, int e0, int n, double half) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= n) return;
+  for (int q = 0; q < 4; ++q) {
+    const int c = col[4 * (e0 + m) + q];
+    if (c < 0) continue;
+    double2& d = B[m + int64_t(c - e0) * n];
+    d.x += half * val[4 * (e0 + m) + q];
+  }
+}
+
+__global__ void k_scale(double2* M, int64_t n, double fr, double fi) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double2 v = M[i];
+  M[i] = make_double2(v.x * fr - v.y * fi, v.x * fi + v.y * fr);
+}
+
+// Back substitution on one diagonal block of an upper-triangular factor:
+// X[i0 : i0+nb, c] = U[i0 : i0+nb, i0 : i0+nb]^{-1} X[i0 : i0+nb, c] for every column c
+// (one thread per column, the block in LDS).  Together with GEMM updates of the rows
+// above it this is the blocked triangular solve without diagonal-block inversion,
+// which stays backward stable for factors whose pivots span many decades.
+constexpr int kUB = 32;
+__global__ void __launch_bounds__(256) k_usolve_block(const double2* U, int64_t ld, int i0, int nb, double2* X,
+                                                     int64_t ldx, int nrhs) {
+  __shared__ double2 blk[kUB][kUB + 1];
+  for (int e = threadIdx.x; e < nb * nb; e += 256) {
+    const int r = e % nb, cc = e / nb;
+    blk[r][cc] = U[(i0 + r) + int64_t(i0 + cc) * ld];
+  }
+  __syncthreads();
+  const int c = blockIdx.x * 256 + threadIdx.x;
+  if (c >= nrhs) return;
+  double2 x[kUB];
+#pragma unroll
+  for (int i = 0; i < kUB; ++i) x[i] = i < nb ? X[(i0 + i) + int64_t(c) * ldx] : make_double2(0.0, 0.0);
+#pragma unroll
+  for (int i = kUB - 1; i >= 0; --i) {
+    if (i >= nb) continue;
+    double2 acc = x[i];
+#pragma unroll
+    for (int j = i + 1; j < kUB; ++j) {
+      if (j >= nb) continue;
+      const double2 u = blk[i][j];
+      acc.x -= u.x * x[j].x - u.y * x[j].y;
+      acc.y -= u.x * x[j].y + u.y * x[j].x;
+    }
+    const double2 d = blk[i][i];
+    const double den = d.x * d.x + d.y * d.y;
+    x[i] = make_double2((acc.x * d.x + acc.y * d.y) / den, (acc.y * d.x - acc.x * d.y) / den);
+  }
+#pragma unroll
+  for (int i = 0; i < kUB; ++i)
+    if (i < nb) X[(i0 + i) + int64_t(c) * ldx] = x[i];
+}
+
+// ---------------------------------------------------------------------------
+// A1 + A2: persistent internal GEMV over the slot queues, fused epilogue.
+// Each workgroup is one slot; it walks its tiles in order.  A wave takes four
+// consecutive rows at a time and streams them with 16-byte loads (two complex
+// per lane), sharing the H loads between the four rows.
+// ---------------------------------------------------------------------------
+struct BlockDev { int64_t off; int32_t n; int32_t e0; };
+
+template <bool F64>
+__global__ void __launch_bounds__(256) k_internal(const float2* __restrict__ hi, const float2* __restrict__ lo,
+                                                  const BlockDev* __restrict__ blocks, const int4* __restrict__ tiles,
+                                                  const int32_t* __restrict__ slot_start, const void* __restrict__ Hv,
+                                                  void* __restrict__ ev, void* __restrict__ jv, void* __restrict__ gv,
+                                                  unsigned long long* __restrict__ stamps) {
+  using T = typename P<F64>::T;
+  const C2<T>* H = reinterpret_cast<const C2<T>*>(Hv);
+  C2<T>* e = reinterpret_cast<C2<T>*>(ev);
+  C2<T>* jo = reinterpret_cast<C2<T>*>(jv);
+  C2<T>* go = reinterpret_cast<C2<T>*>(gv);
+  const int slot = blockIdx.x;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int ti = slot_start[slot]; ti < slot_start[slot + 1]; ++ti) {
+    const int4 tl = tiles[ti];        // block, row0, rows, slot
+    unsigned long long t_start = 0;
+    if (stamps && threadIdx.x == 0) t_start = wall_clock64();
+    const BlockDev B = blocks[tl.x];
+    const int n = B.n, ld = (n + 1) & ~1;
+    const C2<T>* Hs = H + B.e0;
+    for (int r0 = tl.y + 4 * wave; r0 < tl.y + tl.z; r0 += 16) {
+      T ar[4] = {0, 0, 0, 0}, ai[4] = {0, 0, 0, 0};
+      const int nr = min(4, tl.y + tl.z - r0);
+      for (int col = 2 * lane; col < ld; col += 128) {
+        C2<T> h0 = Hs[col], h1 = (col + 1 < n) ? Hs[col + 1] : cz<T>();
+        if (col >= n) h0 = cz<T>();
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          if (q < nr) {
+            const int64_t idx = B.off + int64_t(r0 + q) * ld + col;
+            float4 a = *reinterpret_cast<const float4*>(hi + idx);
+            T a0r = a.x, a0i = a.y, a1r = a.z, a1i = a.w;
+            if (F64) {
+              float4 b = *reinterpret_cast<const float4*>(lo + idx);
+              a0r += T(b.x); a0i += T(b.y); a1r += T(b.z); a1i += T(b.w);
+            }
+            ar[q] += a0r * h0.x - a0i * h0.y + a1r * h1.x - a1i * h1.y;
+            ai[q] += a0r * h0.y + a0i * h0.x + a1r * h1.y + a1i * h1.x;
+          }
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        T sr = wave_sum(ar[q]), si = wave_sum(ai[q]);
+        if (lane == 0 && q < nr) {
+          const int row = r0 + q;
+          if (row < n) {
+            e[B.e0 + row] = {sr, si};
+          } else {
+            const int k = row - n;
+            const C2<T> h = Hs[k];
+            jo[B.e0 + k] = {h.x - sr, h.y - si};     // j = H - M H
+            if (go) go[B.e0 + k] = {sr, si};
+          }
+        }
+      }
+    }
+    if (stamps) {
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        stamps[2 * ti] = t_start;
+        stamps[2 * ti + 1] = wall_clock64();
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// A3: projection P as an atomic-free gather over occupied grid nodes.
+// RWG list: S_c(node) = sum w_c j_n (c = x, y, z); pulse list: S_rho = sum (w A_t) c0rho_t.
+// ---------------------------------------------------------------------------
+template <bool F64>
+__global__ void k_project(const int32_t* pe_node, const int32_t* pe_ptr, const int32_t* pe_idx, const void* pe_w,
+                          int64_t n_pe, const int32_t* pt_node, const int32_t* pt_ptr, const int32_t* pt_idx,
+                          const void* pt_w, int64_t n_pt, const void* jv, const void* rhov, void* octv, int64_t N3) {
+  using T = typename P<F64>::T;
+  const T* we = reinterpret_cast<const T*>(pe_w);
+  const T* wt = reinterpret_cast<const T*>(pt_w);
+  const C2<T>* j = reinterpret_cast<const C2<T>*>(jv);
+  const C2<T>* rho = reinterpret_cast<const C2<T>*>(rhov);
+  C2<T>* oct = reinterpret_cast<C2<T>*>(octv);
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n_pe) {
+    T sx[2] = {0, 0}, sy[2] = {0, 0}, sz[2] = {0, 0};
+    for (int z = pe_ptr[i]; z < pe_ptr[i + 1]; ++z) {
+      const C2<T> v = j[pe_idx[z]];
+      const T w0 = we[3 * int64_t(z)], w1 = we[3 * int64_t(z) + 1], w2 = we[3 * int64_t(z) + 2];
+      sx[0] += w0 * v.x; sx[1] += w0 * v.y;
+      sy[0] += w1 * v.x; sy[1] += w1 * v.y;
+      sz[0] += w2 * v.x; sz[1] += w2 * v.y;
+    }
+    const int64_t node = pe_node[i];
+    oct[node] = {sx[0], sx[1]};
+    oct[N3 + node] = {sy[0], sy[1]};
+    oct[2 * N3 + node] = {sz[0], sz[1]};
+  } else if (i < n_pe + n_pt) {
+    const int64_t k = i - n_pe;
+    T s[2] = {0, 0};
+    for (int z = pt_ptr[k]; z < pt_ptr[k + 1]; ++z) {
+      const C2<T> v = rho[pt_idx[z]];
+      s[0] += wt[z] * v.x;
+      s[1] += wt[z] * v.y;
+    }
+    oct[3 * N3 + pt_node[k]] = {s[0], s[1]};
+  }
+}
+
+// ---------------------------------------------------------------------------
+// A5 + A6 for pulses: phi_t = W_rho Phi_rho + L_phi,NR (B c0rho); one wave per row.
+// ---------------------------------------------------------------------------
+template <bool F64>
+__global__ void __launch_bounds__(256) k_phi(const int32_t* wt_base, const void* wt_w, const void* octv, int64_t N3,
+                                             int Nx, int NxNy, const int64_t* ptr, const int32_t* col,
+                                             const void* valv, const void* rhov, void* phiv, int64_t n_t) {
+  using T = typename P<F64>::T;
+  const int64_t t = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (t >= n_t) return;
+  const T* w = reinterpret_cast<const T*>(wt_w);
+  const C2<T>* Phi = reinterpret_cast<const C2<T>*>(octv) + 3 * N3;
+  const C2<T>* val = reinterpret_cast<const C2<T>*>(valv);
+  const C2<T>* rho = reinterpret_cast<const C2<T>*>(rhov);
+  T sr = 0, si = 0;
+  if (lane < 27) {
+    const int64_t node = wt_base[t] + (lane % 3) + Nx * ((lane / 3) % 3) + int64_t(NxNy) * (lane / 9);
+    const T wv = w[27 * t + lane];
+    sr = wv * Phi[node].x;
+    si = wv * Phi[node].y;
+  }
+  for (int64_t z = ptr[t] + lane; z < ptr[t + 1]; z += 64) {
+    const C2<T> a = val[z], b = rho[col[z]];
+    sr += a.x * b.x - a.y * b.y;
+    si += a.x * b.y + a.y * b.x;
+  }
+  sr = wave_sum(sr);
+  si = wave_sum(si);
+  if (lane == 0) reinterpret_cast<C2<T>*>(phiv)[t] = {sr, si};
+}
+
+// ---------------------------------------------------------------------------
+// A5 + A6 + A7 for RWG rows: a = W_A Phi + L_A,NR j;
+// y1 = j k0 a + l (phi[T+] - phi[T-]) + I_x e / eta0  (written as complex128).
+// ---------------------------------------------------------------------------
+template <bool F64, bool AIM>
+__global__ void __launch_bounds__(256) k_rows_A(const int32_t* we_base, const void* we_w, const void* octv, int64_t N3,
+                                                int Nx, int NxNy, const int64_t* ptr, const int32_t* col,
+                                                const void* valv, const void* jv, const void* a_dense,
+                                                const void* phiv, const void* ev, const int32_t* tplus,
+                                                const int32_t* tminus, const double* len, const int32_t* ix_col,
+                                                const double* ix_val, double k0, double inv_eta0, void* av,
+                                                double2* y, int64_t n_e) {
+  using T = typename P<F64>::T;
+  const int64_t m = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (m >= n_e) return;
+  T sr = 0, si = 0;
+  if (AIM) {
+    const T* w = reinterpret_cast<const T*>(we_w) + 81 * m;
+    const C2<T>* Phi = reinterpret_cast<const C2<T>*>(octv);
+    if (lane < 27) {
+      const int64_t node = we_base[m] + (lane % 3) + Nx * ((lane / 3) % 3) + int64_t(NxNy) * (lane / 9);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const C2<T> p = Phi[c * N3 + node];
+        sr += w[c * 27 + lane] * p.x;
+        si += w[c * 27 + lane] * p.y;
+      }
+    }
+    const C2<T>* val = reinterpret_cast<const C2<T>*>(valv);
+    const C2<T>* j = reinterpret_cast<const C2<T>*>(jv);
+    for (int64_t z = ptr[m] + lane; z < ptr[m + 1]; z += 64) {
+      const C2<T> a = val[z], b = j[col[z]];
+      sr += a.x * b.x - a.y * b.y;
+      si += a.x * b.y + a.y * b.x;
+    }
+    sr = wave_sum(sr);
+    si = wave_sum(si);
+  } else if (lane == 0) {
+    const C2<T> a = reinterpret_cast<const C2<T>*>(a_dense)[m];
+    sr = a.x;
+    si = a.y;
+  }
+  if (lane == 0) {
+    const C2<T>* phi = reinterpret_cast<const C2<T>*>(phiv);
+    const C2<T>* e = reinterpret_cast<const C2<T>*>(ev);
+    if (AIM) reinterpret_cast<C2<T>*>(av)[m] = {sr, si};
+    const double l = len[m];
+    const C2<T> pp = phi[tplus[m]], pm = phi[tminus[m]];
+    double yr = -k0 * double(si) + l * (double(pp.x) - double(pm.x));
+    double yi = k0 * double(sr) + l * (double(pp.y) - double(pm.y));
+    for (int q = 0; q < 4; ++q) {
+      const int c = ix_col[4 * m + q];
+      if (c < 0) continue;
+      const C2<T> ec = e[c];
+      yr += inv_eta0 * ix_val[4 * m + q] * double(ec.x);
+      yi += inv_eta0 * ix_val[4 * m + q] * double(ec.y);
+    }
+    y[m] = make_double2(yr, yi);
+  }
+}
+
+// y2 = F D j + j k0 c0rho = -(1/A_t) sum_i s_i l_i j_i + j k0 c0rho_t
+template <bool F64>
+__global__ void k_rows_T(const int32_t* tri_edge, const int8_t* tri_sign, const double* len, const double* area,
+                         const void* jv, const void* rhov, double k0, double2* y2, int64_t n_t) {
+  using T = typename P<F64>::T;
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= n_t) return;
+  const C2<T>* j = reinterpret_cast<const C2<T>*>(jv);
+  const C2<T> r = reinterpret_cast<const C2<T>*>(rhov)[t];
+  double dr = 0.0, di = 0.0;
+  for (int i = 0; i < 3; ++i) {
+    const int n = tri_edge[3 * t + i];
+    const double d = tri_sign[3 * t + i] * len[n];
+    dr += d * double(j[n].x);
+    di += d * double(j[n].y);
+  }
+  const double ia = 1.0 / area[t];
+  y2[t] = make_double2(-ia * dr - k0 * double(r.y), -ia * di + k0 * double(r.x));
+}
+
+// Dense row-major GEMV (plain mode): out = A v, A as hi (+ lo), one wave per row.
+template <bool F64>
+__global__ void __launch_bounds__(256) k_dense_gemv(const float2* hi, const float2* lo, int64_t n, const void* vv,
+                                                    const double* colscale, void* outv) {
+  using T = typename P<F64>::T;
+  const int64_t r = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (r >= n) return;
+  const C2<T>* v = reinterpret_cast<const C2<T>*>(vv);
+  T sr = 0, si = 0;
+  for (int64_t c = lane; c < n; c += 64) {
+    float2 a = hi[r * n + c];
+    T ar = a.x, ai = a.y;
+    if (F64) { float2 b = lo[r * n + c]; ar += T(b.x); ai += T(b.y); }
+    C2<T> x = v[c];
+    if (colscale) { x.x *= T(colscale[c]); x.y *= T(colscale[c]); }
+    sr += ar * x.x - ai * x.y;
+    si += ar * x.y + ai * x.x;
+  }
+  sr = wave_sum(sr);
+  si = wave_sum(si);
+  if (lane == 0) reinterpret_cast<C2<T>*>(outv)[r] = {sr, si};
+}
+
+template <bool F64>
+__global__ void k_copy_out(const void* in, double2* out, int64_t n) {
+  using T = typename P<F64>::T;
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const C2<T> v = reinterpret_cast<const C2<T>*>(in)[i];
+  out[i] = make_double2(double(v.x), double(v.y));
+}
+
+template <bool F64>
+void internal_launch(Ctx& c, const void* H, void* e, void* j, void* g, hipStream_t s) {
+  unsigned long long* st = c.record ? c.d_stamps.as<unsigned long long>() : nullptr;
+  hipLaunchKernelGGL(k_internal<F64>, dim3(unsigned(c.slots)), dim3(256), 0, s, c.d_hi.as<float2>(),
+                     c.d_lo.as<float2>(), c.d_blocks.as<BlockDev>(), c.d_tiles.as<int4>(),
+                     c.d_slot_start.as<int32_t>(), H, e, j, g, st);
+  SLIM_HIP(hipGetLastError());
+}
+
+template <bool F64>
+void matvec_t(Ctx& c, const void* x, void* y, void* e_out, void* g_out, void* a_out, void* phi_out, hipStream_t s) {
+  const RWGTable& r = c.rwg;
+  const int64_t ne = r.n_e, nt = r.n_t, nsys = ne + nt;
+  const size_t es = F64 ? 16 : 8;
+  const void* X = x;
+  if (!F64) {
+    hipLaunchKernelGGL(k_c128_to_c64, dim3(nblk(nsys)), dim3(256), 0, s, reinterpret_cast<const double2*>(x),
+                       c.d_x64.as<float2>(), nsys);
+    SLIM_HIP(hipGetLastError());
+    X = c.d_x64.p;
+  }
+  const char* Xc = reinterpret_cast<const char*>(X);
+  const void* rho = Xc + ne * es;
+  double2* Y = reinterpret_cast<double2*>(y);
+  // A1 + A2
+  internal_launch<F64>(c, X, c.d_e.p, c.d_j.p, g_out ? c.d_g.p : nullptr, s);
+  const double inv_eta0 = 1.0 / eta0();
+  if (c.plain) {
+    hipLaunchKernelGGL(k_dense_gemv<F64>, dim3(nblk(nt, 4)), dim3(256), 0, s, c.d_Lphi_hi.as<float2>(),
+                       c.d_Lphi_lo.as<float2>(), nt, rho, c.d_area.as<double>(), c.d_phi.p);
+    hipLaunchKernelGGL(k_dense_gemv<F64>, dim3(nblk(ne, 4)), dim3(256), 0, s, c.d_LA_hi.as<float2>(),
+                       c.d_LA_lo.as<float2>(), ne, c.d_j.p, nullptr, c.d_a.p);
+    SLIM_HIP(hipGetLastError());
+    hipLaunchKernelGGL((k_rows_A<F64, false>), dim3(nblk(ne, 4)), dim3(256), 0, s, nullptr, nullptr, nullptr,
+                       int64_t(0), 0, 0, nullptr, nullptr, nullptr, nullptr, c.d_a.p, c.d_phi.p, c.d_e.p,
+                       c.d_tplus.as<int32_t>(), c.d_tminus.as<int32_t>(), c.d_len.as<double>(),
+                       c.d_ix_col.as<int32_t>(), c.d_ix_val.as<double>(), c.k0, inv_eta0, nullptr, Y, ne);
+  } else {
+    const int64_t N3 = c.grid.nodes();
+    void* oct_in = F64 ? c.d_oct_in.p : c.d_oct_in32.p;
+    hipLaunchKernelGGL(k_project<F64>, dim3(nblk(c.n_pe_nodes + c.n_pt_nodes)), dim3(256), 0, s,
+                       c.d_pe_node.as<int32_t>(), c.d_pe_ptr.as<int32_t>(), c.d_pe_idx.as<int32_t>(),
+                       F64 ? c.d_pe_w64.p : c.d_pe_w32.p, c.n_pe_nodes, c.d_pt_node.as<int32_t>(),
+                       c.d_pt_ptr.as<int32_t>(), c.d_pt_idx.as<int32_t>(), F64 ? c.d_pt_w64.p : c.d_pt_w32.p,
+                       c.n_pt_nodes, c.d_j.p, rho, oct_in, N3);
+    SLIM_HIP(hipGetLastError());
+    aim_convolve(c, F64, 4, s);
+    const int Nx = c.grid.N[0], NxNy = c.grid.N[0] * c.grid.N[1];
+    hipLaunchKernelGGL(k_phi<F64>, dim3(nblk(nt, 4)), dim3(256), 0, s, c.d_wt_base.as<int32_t>(),
+                       F64 ? c.d_wt_w64.p : c.d_wt_w32.p, c.d_oct_out.p, N3, Nx, NxNy, c.d_nP_ptr.as<int64_t>(),
+                       c.d_nP_col.as<int32_t>(), F64 ? c.d_nP_v128.p : c.d_nP_v64.p, rho, c.d_phi.p, nt);
+    SLIM_HIP(hipGetLastError());
+    hipLaunchKernelGGL((k_rows_A<F64, true>), dim3(nblk(ne, 4)), dim3(256), 0, s, c.d_we_base.as<int32_t>(),
+                       F64 ? c.d_we_w64.p : c.d_we_w32.p, c.d_oct_out.p, N3, Nx, NxNy, c.d_nA_ptr.as<int64_t>(),
+                       c.d_nA_col.as<int32_t>(), F64 ? c.d_nA_v128.p : c.d_nA_v64.p, c.d_j.p, nullptr, c.d_phi.p,
+                       c.d_e.p, c.d_tplus.as<int32_t>(), c.d_tminus.as<int32_t>(), c.d_len.as<double>(),
+                       c.d_ix_col.as<int32_t>(), c.d_ix_val.as<double>(), c.k0, inv_eta0, c.d_a.p, Y, ne);
+  }
+  SLIM_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_rows_T<F64>, dim3(nblk(nt)), dim3(256), 0, s, c.d_tri_edge.as<int32_t>(),
+                     c.d_tri_sign.as<int8_t>(), c.d_len.as<double>(), c.d_area.as<double>(), c.d_j.p, rho, c.k0,
+                     Y + ne, nt);
+  SLIM_HIP(hipGetLastError());
+  auto out = [&](const void* src, void* dst, int64_t n) {
+    if (!dst) return;
+    hipLaunchKernelGGL(k_copy_out<F64>, dim3(nblk(n)), dim3(256), 0, s, src, reinterpret_cast<double2*>(dst), n);
+    SLIM_HIP(hipGetLastError());
+  };
+  out(c.d_e.p, e_out, ne);
+  out(c.d_g.p, g_out, ne);
+  out(c.d_a.p, a_out, ne);
+  out(c.d_phi.p, phi_out, nt);
+}
+
+}  // namespace
+
+void launch_cast_c128_to_c64(const void* in, void* out, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_c128_to_c64, dim3(nblk(n)), dim3(256), 0, s, reinterpret_cast<const double2*>(in),
+                     reinterpret_cast<float2*>(out), n);
+  SLIM_HIP(hipGetLastError());
+}
+void launch_cast_c64_to_c128(const void* in, void* out, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_c64_to_c128, dim3(nblk(n)), dim3(256), 0, s, reinterpret_cast<const float2*>(in),
+                     reinterpret_cast<double2*>(out), n);
+  SLIM_HIP(hipGetLastError());
+}
+void launch_pack_block(const double* Z, const double* M, int n, Cplx<float>* hi, Cplx<float>* lo, hipStream_t s) {
+  const int ld = (n + 1) & ~1;
+  const int64_t tot = int64_t(2 * n) * ld;
+  hipLaunchKernelGGL(k_pack_block, dim3(nblk(tot)), dim3(256), 0, s, reinterpret_cast<const double2*>(Z),
+                     reinterpret_cast<const double2*>(M), n, ld, reinterpret_cast<float2*>(hi),
+                     reinterpret_cast<float2*>(lo));
+  SLIM_HIP(hipGetLastError());
+}
+void launch_pack_dense(const double* A, int64_t rows, int64_t cols, Cplx<float>* hi, Cplx<float>* lo, hipStream_t s) {
+  const int64_t n = rows * cols;
+  hipLaunchKernelGGL(k_pack_dense, dim3(nblk(n)), dim3(256), 0, s, reinterpret_cast<const double2*>(A), n,
+                     reinterpret_cast<float2*>(hi), reinterpret_cast<float2*>(lo));
+  SLIM_HIP(hipGetLastError());
+}
+void launch_add_scaled_ix(double* B, const int32_t* col, const double* val, int e0, int n, double half, hipStream_t s) {
+  hipLaunchKernelGGL(k_add_ix, dim3(nblk(n)), dim3(256), 0, s, reinterpret_cast<double2*>(B), col, val, e0, n, half);
+  SLIM_HIP(hipGetLastError());
+}
+void launch_usolve_block(const double* U, int64_t ld, int i0, int nb, double* X, int64_t ldx, int nrhs, hipStream_t s) {
+  hipLaunchKernelGGL(k_usolve_block, dim3(nblk(nrhs)), dim3(256), 0, s, reinterpret_cast<const double2*>(U), ld, i0, nb,
+                     reinterpret_cast<double2*>(X), ldx, nrhs);
+  SLIM_HIP(hipGetLastError());
+}
+void launch_scale(double* M, int64_t n, cd f, hipStream_t s) {
+  hipLaunchKernelGGL(k_scale, dim3(nblk(n)), dim3(256), 0, s, reinterpret_cast<double2*>(M), n, f.real(), f.imag());
+  SLIM_HIP(hipGetLastError());
+}
+
+void matvec(Ctx& c, slim_prec prec, const void* x, void* y, void* e_out, void* g_out, void* a_out, void* phi_out,
+            hipStream_t s) {
+  if (prec == SLIM_FP64) matvec_t<true>(c, x, y, e_out, g_out, a_out, phi_out, s);
+  else matvec_t<false>(c, x, y, e_out, g_out, a_out, phi_out, s);
+}
+
+// Internal part alone: H (complex128) -> e = Z H, g = M H (complex128 outputs).
+void internal_apply(Ctx& c, slim_prec prec, const void* H, void* e, void* g, hipStream_t s, bool /*h_is_c128*/) {
+  const int64_t ne = c.rwg.n_e;
+  if (prec == SLIM_FP64) {
+    internal_launch<true>(c, H, c.d_e.p, c.d_j.p, c.d_g.p, s);
+    if (e) hipLaunchKernelGGL(k_copy_out<true>, dim3(nblk(ne)), dim3(256), 0, s, c.d_e.p, reinterpret_cast<double2*>(e), ne);
+    if (g) hipLaunchKernelGGL(k_copy_out<true>, dim3(nblk(ne)), dim3(256), 0, s, c.d_g.p, reinterpret_cast<double2*>(g), ne);
+  } else {
+    launch_cast_c128_to_c64(H, c.d_x64.p, ne, s);
+    internal_launch<false>(c, c.d_x64.p, c.d_e.p, c.d_j.p, c.d_g.p, s);
+    if (e) hipLaunchKernelGGL(k_copy_out<false>, dim3(nblk(ne)), dim3(256), 0, s, c.d_e.p, reinterpret_cast<double2*>(e), ne);
+    if (g) hipLaunchKernelGGL(k_copy_out<false>, dim3(nblk(ne)), dim3(256), 0, s, c.d_g.p, reinterpret_cast<double2*>(g), ne);
+  }
+  SLIM_HIP(hipGetLastError());
+}
+
+}  // namespace slim

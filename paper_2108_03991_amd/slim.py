@@ -1,0 +1,236 @@
+"""Python binding of libslim.so (argument marshalling only).
+
+Every step of the product runs in the HIP library; this module converts
+numpy arrays and torch device tensors into the plain pointers and sizes of the
+C ABI declared in include/slim.h.  It raises if the library is missing: there
+is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libslim.so")
+
+SLIM_FP64, SLIM_MIXED = 0, 1
+STATUS = {0: "SLIM_OK", 1: "SLIM_E_ARG", 2: "SLIM_E_MESH", 3: "SLIM_E_STATE", 4: "SLIM_E_OOM", 5: "SLIM_E_HIP",
+          6: "SLIM_E_NUMERIC", 7: "SLIM_E_NOT_CONVERGED", 8: "SLIM_E_UNSUPPORTED"}
+
+
+class SlimError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s: %s" % (STATUS.get(code, code), msg))
+        self.code = code
+
+
+class BuildOpts(C.Structure):
+    _fields_ = [("freq", C.c_double), ("grid", C.c_int32 * 3), ("near_cheb", C.c_int32),
+                ("n_far", C.c_int32), ("n_near", C.c_int32), ("levels", C.c_int32), ("n_r", C.c_int32),
+                ("n_t", C.c_int32), ("q", C.c_double), ("c_near", C.c_double), ("sched_mode", C.c_int32),
+                ("tile_rows", C.c_int32), ("internal_kernel", C.c_int32), ("slots", C.c_int32),
+                ("mem_budget", C.c_int64), ("verbose", C.c_int32)]
+
+
+class Layout(C.Structure):
+    _fields_ = [("n_e", C.c_int64), ("n_t", C.c_int64), ("n_sys", C.c_int64), ("n_obj", C.c_int32),
+                ("grid", C.c_int32 * 3), ("grid_h", C.c_double * 3), ("grid_origin", C.c_double * 3),
+                ("nnz_near_A", C.c_int64), ("nnz_near_phi", C.c_int64), ("internal_entries", C.c_int64),
+                ("n_tiles", C.c_int64), ("slots", C.c_int32), ("tile_rows", C.c_int32), ("mean_edge", C.c_double),
+                ("build_seconds", C.c_double), ("device_bytes", C.c_int64)]
+
+
+class SolveOpts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("restart", C.c_int32), ("max_iter", C.c_int32), ("prec", C.c_int32),
+                ("inner_tol", C.c_double), ("max_outer", C.c_int32)]
+
+
+class SolveInfo(C.Structure):
+    _fields_ = [("iterations", C.c_int32), ("outer_steps", C.c_int32), ("rel_residual", C.c_double),
+                ("seconds", C.c_double), ("matvec_seconds", C.c_double), ("n_matvec_fp64", C.c_int32),
+                ("n_matvec_mixed", C.c_int32)]
+
+
+class Material(C.Structure):
+    _fields_ = [("sigma", C.c_double), ("eps_r", C.c_double), ("mu_r", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libslim.so is not built (run __graft_entry__.build()); there is no fallback")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, i64, dp = C.c_void_p, C.c_int32, C.c_int64, C.POINTER(C.c_double)
+        L.slim_create.argtypes = [i32, C.POINTER(vp)]
+        L.slim_destroy.argtypes = [vp]
+        L.slim_destroy.restype = None
+        L.slim_last_error.argtypes = [vp]
+        L.slim_last_error.restype = C.c_char_p
+        L.slim_default_build_opts.argtypes = [C.POINTER(BuildOpts)]
+        L.slim_default_build_opts.restype = None
+        L.slim_set_mesh.argtypes = [vp, vp, i64, vp, i64, vp, i32]
+        L.slim_set_materials.argtypes = [vp, vp]
+        L.slim_build.argtypes = [vp, C.POINTER(BuildOpts)]
+        L.slim_get_layout.argtypes = [vp, C.POINTER(Layout)]
+        L.slim_get_rwg.argtypes = [vp, vp, vp, vp]
+        L.slim_matvec.argtypes = [vp, i32, vp, vp, vp]
+        L.slim_matvec_parts.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp]
+        L.slim_internal_apply.argtypes = [vp, i32, vp, vp, vp, dp, vp]
+        L.slim_rhs_planewave.argtypes = [vp, dp, dp, vp, vp]
+        L.slim_solve.argtypes = [vp, vp, i32, vp, C.POINTER(SolveOpts), C.POINTER(SolveInfo), vp]
+        L.slim_sched_record.argtypes = [vp, i32]
+        L.slim_sched_tiles.argtypes = [vp, dp, C.POINTER(i64)]
+        L.slim_sched_train.argtypes = [vp, i32, C.c_double, dp]
+        L.slim_sched_set_mode.argtypes = [vp, i32]
+        L.slim_mlp_forward_backward.argtypes = [i32, i32, vp, vp, vp, vp, vp, vp, vp]
+        for name in ("slim_create", "slim_set_mesh", "slim_set_materials", "slim_build", "slim_get_layout",
+                     "slim_get_rwg", "slim_matvec", "slim_matvec_parts", "slim_internal_apply",
+                     "slim_rhs_planewave", "slim_solve", "slim_sched_record", "slim_sched_tiles",
+                     "slim_sched_train", "slim_sched_set_mode", "slim_mlp_forward_backward"):
+            getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+EXPORTS = ["slim_default_build_opts", "slim_create", "slim_destroy", "slim_last_error", "slim_set_mesh",
+           "slim_set_materials", "slim_build", "slim_get_layout", "slim_get_rwg", "slim_matvec",
+           "slim_matvec_parts", "slim_internal_apply", "slim_rhs_planewave", "slim_solve", "slim_sched_record",
+           "slim_sched_tiles", "slim_sched_train", "slim_sched_set_mode", "slim_mlp_forward_backward"]
+
+
+def _ptr(t):
+    """Device pointer of a torch tensor (or None)."""
+    if t is None:
+        return None
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    return C.c_void_p(stream)
+
+
+def default_build_opts(**kw):
+    o = BuildOpts()
+    lib().slim_default_build_opts(C.byref(o))
+    for k, v in kw.items():
+        if k == "grid":
+            o.grid[0], o.grid[1], o.grid[2] = (int(x) for x in v)
+        else:
+            setattr(o, k, v)
+    return o
+
+
+class Context:
+    def __init__(self, device=0):
+        self._h = C.c_void_p()
+        st = lib().slim_create(int(device), C.byref(self._h))
+        if st != 0:
+            raise SlimError(st, "slim_create failed")
+
+    def close(self):
+        if self._h:
+            lib().slim_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st):
+        if st != 0:
+            raise SlimError(st, lib().slim_last_error(self._h).decode())
+
+    def set_mesh(self, verts, tris, obj, n_obj):
+        v = np.ascontiguousarray(verts, dtype=np.float64)
+        t = np.ascontiguousarray(tris, dtype=np.int32)
+        o = np.ascontiguousarray(obj, dtype=np.int32)
+        self._check(lib().slim_set_mesh(self._h, v.ctypes.data, v.shape[0], t.ctypes.data, t.shape[0],
+                                        o.ctypes.data, int(n_obj)))
+
+    def set_materials(self, mats=None):
+        if mats is None:
+            self._check(lib().slim_set_materials(self._h, None))
+            return
+        arr = (Material * len(mats))(*[Material(*m) for m in mats])
+        self._check(lib().slim_set_materials(self._h, C.cast(arr, C.c_void_p)))
+
+    def build(self, **kw):
+        o = default_build_opts(**kw)
+        self._check(lib().slim_build(self._h, C.byref(o)))
+        return self.layout()
+
+    def layout(self):
+        L = Layout()
+        self._check(lib().slim_get_layout(self._h, C.byref(L)))
+        return L
+
+    def rwg(self, n_e):
+        ev = np.zeros(2 * n_e, dtype=np.int32)
+        tp = np.zeros(n_e, dtype=np.int32)
+        tm = np.zeros(n_e, dtype=np.int32)
+        self._check(lib().slim_get_rwg(self._h, ev.ctypes.data, tp.ctypes.data, tm.ctypes.data))
+        return ev.reshape(-1, 2), tp, tm
+
+    def matvec(self, prec, x, y, stream=None):
+        self._check(lib().slim_matvec(self._h, prec, _ptr(x), _ptr(y), _stream(stream)))
+
+    def matvec_parts(self, prec, x, y, e=None, g=None, a=None, phi=None, stream=None):
+        self._check(lib().slim_matvec_parts(self._h, prec, _ptr(x), _ptr(y), _ptr(e), _ptr(g), _ptr(a), _ptr(phi),
+                                            _stream(stream)))
+
+    def internal_apply(self, prec, H, e=None, g=None, timed=False, stream=None):
+        ms = C.c_double(0.0)
+        self._check(lib().slim_internal_apply(self._h, prec, _ptr(H), _ptr(e), _ptr(g),
+                                              C.byref(ms) if timed else None, _stream(stream)))
+        return ms.value if timed else None
+
+    def rhs_planewave(self, khat, epol, b, stream=None):
+        k = (C.c_double * 3)(*khat)
+        e = (C.c_double * 3)(*epol)
+        self._check(lib().slim_rhs_planewave(self._h, k, e, _ptr(b), _stream(stream)))
+
+    def solve(self, b, x, tol=1e-6, restart=50, max_iter=1000, prec=SLIM_FP64, inner_tol=1e-4, max_outer=0,
+              scaled_rhs=False, stream=None):
+        o = SolveOpts(tol, restart, max_iter, prec, inner_tol, max_outer)
+        info = SolveInfo()
+        st = lib().slim_solve(self._h, _ptr(b), int(bool(scaled_rhs)), _ptr(x), C.byref(o), C.byref(info),
+                              _stream(stream))
+        if st not in (0, 7):
+            self._check(st)
+        return info, st == 0
+
+    def sched_record(self, on=True):
+        self._check(lib().slim_sched_record(self._h, int(bool(on))))
+
+    def sched_tiles(self):
+        n = C.c_int64(0)
+        self._check(lib().slim_sched_tiles(self._h, None, C.byref(n)))
+        out = np.zeros(7 * n.value, dtype=np.float64)
+        self._check(lib().slim_sched_tiles(self._h, out.ctypes.data_as(C.POINTER(C.c_double)), C.byref(n)))
+        return out.reshape(-1, 7)
+
+    def sched_train(self, epochs=2000, lr=3e-3):
+        loss = C.c_double(0.0)
+        self._check(lib().slim_sched_train(self._h, int(epochs), float(lr), C.byref(loss)))
+        return loss.value
+
+    def sched_set_mode(self, mode):
+        self._check(lib().slim_sched_set_mode(self._h, int(mode)))
+
+
+def mlp_forward_backward(F, B, params, X, t, y, grad, loss, stream=None):
+    st = lib().slim_mlp_forward_backward(int(F), int(B), _ptr(params), _ptr(X), _ptr(t), _ptr(y), _ptr(grad),
+                                         _ptr(loss), _stream(stream))
+    if st != 0:
+        raise SlimError(st, "slim_mlp_forward_backward failed")
