@@ -79,20 +79,22 @@ OFFS = np.array([(dx, dy, dz) for dz in (-1, 0, 1) for dy in (-1, 0, 1) for dx i
 ALPHAS = np.array([(ax, ay, az) for az in range(3) for ay in range(3) for ax in range(3)])
 
 
-def _moment_matrix(h):
-    """V[alpha, node] = prod_c (offset_c h_c)^alpha_c for the 27 stencil nodes."""
-    d = OFFS * h[None, :]
-    return np.prod(d[None, :, :] ** ALPHAS[:, None, :], axis=2)
+def _moment_matrix():
+    """V[alpha, node] = prod_c offset_c^alpha_c for the 27 stencil nodes (offsets in units of h)."""
+    return np.prod(OFFS[None, :, :].astype(float) ** ALPHAS[:, None, :], axis=2)
 
 
 def stencil_weights(grid: Grid, g: RWG, order=5):
     """Solve the 27x27 moment systems for every RWG (3 components) and pulse.
 
+    The moments are taken in grid units, sum_g w_g ((r_g - r0)/h)^alpha =
+    int f ((r - r0)/h)^alpha dS, which is the same linear condition as in metres
+    but keeps the Vandermonde matrix O(1) (in metres its rows differ by h^6).
     Returns (cidx_e (N_E,3), wE (N_E, 3 comps, 27), cidx_t (N_T,3), wT (N_T, 27)).
     """
     rcE, rcT = basis_centres(g)
     cE, cT = stencil_centre(grid, rcE), stencil_centre(grid, rcT)
-    V = _moment_matrix(grid.h)
+    V = _moment_matrix()
     Vt = g.verts[g.tris]
     pts, w = tri_points(Vt, order)                       # (N_T, q, 3), (N_T, q)
     # RWG components: moments accumulated from both triangles
@@ -100,12 +102,12 @@ def stencil_weights(grid: Grid, g: RWG, order=5):
     for i in range(3):
         n = g.tri_edge[:, i]
         r0 = grid.node_pos(cE[n])                         # (N_T,3)
-        rel = pts - r0[:, None, :]
+        rel = (pts - r0[:, None, :]) / grid.h
         mono = np.prod(rel[:, :, None, :] ** ALPHAS[None, None, :, :], axis=3)   # (N_T,q,27)
         f = (g.tri_sign[:, i] * g.length[n] / (2.0 * g.area))[:, None, None] * (pts - Vt[:, i][:, None, :])
         np.add.at(momE, n, np.einsum('tq,tqc,tqa->tca', w, f, mono))
     r0 = grid.node_pos(cT)
-    rel = pts - r0[:, None, :]
+    rel = (pts - r0[:, None, :]) / grid.h
     mono = np.prod(rel[:, :, None, :] ** ALPHAS[None, None, :, :], axis=3)
     momT = np.einsum('tq,tqa->ta', w, mono) / g.area[:, None]
     wE = np.linalg.solve(V[None, None], momE[..., None])[..., 0]
@@ -224,3 +226,49 @@ def build_aim(g: RWG, grid: Grid, k0, LA_exact, Lphi_exact):
     LA_nr = sp.csr_matrix((vA, (m, n)), shape=(g.n_e, g.n_e))
     Lphi_nr = sp.csr_matrix((vP, (t, u)), shape=(g.n_t, g.n_t))
     return AIMOperator(grid, k0, Pc, Pr, Ghat, LA_nr, Lphi_nr)
+
+
+def exact_entries(g: RWG, k0, m, n, qp=None):
+    """Exact L_A[m, n] (RWG pairs) from the triangle-pair integrals, without the dense matrix.
+
+    Each triangle pair is integrated with the lower triangle index as test
+    triangle (the orientation of the dense assembly) and transposed otherwise.
+    """
+    from .operators import triangle_pair_integrals
+    from .quad import QuadParams
+    qp = qp or QuadParams()
+    m = np.asarray(m)
+    n = np.asarray(n)
+    Tm = np.stack([g.tplus[m], g.tminus[m]], 1)
+    Tn = np.stack([g.tplus[n], g.tminus[n]], 1)
+    keys = []
+    for a in range(2):
+        for b in range(2):
+            t, u = Tm[:, a], Tn[:, b]
+            keys.append(np.stack([np.minimum(t, u), np.maximum(t, u)], 1))
+    allk = np.unique(np.concatenate(keys), axis=0)
+    IA, IS, _ = triangle_pair_integrals(g, allk[:, 0], allk[:, 1], k0, qp, want_k=False)
+    key = allk[:, 0] * np.int64(g.n_t) + allk[:, 1]
+    out = np.zeros(m.size, dtype=complex)
+    for a in range(2):
+        for b in range(2):
+            t, u = Tm[:, a], Tn[:, b]
+            i = np.argmax(g.tri_edge[t] == m[:, None], axis=1)
+            j = np.argmax(g.tri_edge[u] == n[:, None], axis=1)
+            p = np.searchsorted(key, np.minimum(t, u) * np.int64(g.n_t) + np.maximum(t, u))
+            v = np.where(t <= u, IA[p, i, j], IA[p, j, i])
+            out += (g.tri_sign[t, i] * g.tri_sign[u, j] * g.length[m] * g.length[n]
+                    / (4.0 * g.area[t] * g.area[u])) * v
+    return out
+
+
+def exact_phi_entries(g: RWG, k0, t, u, qp=None):
+    """Exact L_phi[t, u] = IS / (A_t A_u) for triangle pairs."""
+    from .operators import triangle_pair_integrals
+    from .quad import QuadParams
+    qp = qp or QuadParams()
+    t = np.asarray(t)
+    u = np.asarray(u)
+    lo, hi = np.minimum(t, u), np.maximum(t, u)
+    _, IS, _ = triangle_pair_integrals(g, lo, hi, k0, qp, want_k=False)
+    return IS / (g.area[t] * g.area[u])
