@@ -1,0 +1,243 @@
+"""Benchmark of the SLIM system matrix-vector product on one MI355X.
+
+One step = one full product y = A x of eq. (7)-(8) (internal blocks, AIM
+projection, FFT convolution, interpolation, near field, sparse combine) on the
+seeded synthetic workload, inputs resident in HBM.  Prints one JSON line.
+
+    python bench.py [--steps K] [--warmup W] [--workload conductors] [--solve]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "AIM+internal matvecs/sec and GMRES time-to-1e-6 at ~1M unknowns, mixed vs FP64"
+HBM_PEAK = 8.0e12
+
+WORKLOADS = {
+    # name: (generator kwargs, frequency, AIM grid)
+    "conductors": (dict(seed=0), 5e9, (256, 256, 256)),
+    "line_bundle": (dict(seed=0), 1e9, (128, 128, 128)),
+    "srr_array": (dict(), 100e9, (64, 64, 64)),
+    "bar": (dict(), 10e9, (0, 0, 0)),
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def make_mesh(name, kw):
+    from inputs import geometry
+    gen = {"conductors": geometry.conductors_c5, "line_bundle": geometry.line_bundle_c3,
+           "srr_array": geometry.srr_array_c2, "bar": geometry.bar_c1}[name]
+    return gen(**kw)
+
+
+def algorithmic_bytes(mesh, lay, mixed):
+    """Bytes the method must move per product (unit figures: the design doc, measurement)."""
+    n = np.bincount(mesh.obj)  # triangles per object
+    ne_i = (1.5 * n).astype(np.float64)
+    sc = 8.0 if mixed else 16.0          # complex element (hi, or hi + lo / complex128)
+    b_int = float(np.sum(2.0 * ne_i * ne_i)) * sc + 3.0 * lay.n_e * sc
+    out = dict(internal=b_int)
+    if lay.grid[0] > 0:
+        N3 = float(lay.grid[0] * lay.grid[1] * lay.grid[2])
+        out["fft"] = 4 * 26 * N3 * sc + 8 * N3 * sc
+        ws = 4.0 if mixed else 8.0
+        out["project"] = lay.n_e * 81 * (ws + 4 / 3) + lay.n_t * 27 * (ws + 4) + 4 * N3 * sc
+        nnz = lay.nnz_near_A + lay.nnz_near_phi
+        out["near_rows"] = nnz * (sc + 4) + (lay.n_e + lay.n_t) * (8 + sc * 4) + lay.n_e * 81 * ws + lay.n_t * 27 * ws
+    return out
+
+
+def cpu_baseline(mesh, lay, freq, grid):
+    """The FP64 oracle timed on a bounded sample of the same workload, extrapolated per product."""
+    from threadpoolctl import threadpool_info
+    from oracle.aim import Grid, circulant_kernel, convolve_fft
+    from oracle.operators import Physics, interior_blocks
+    from oracle.rwg import build_rwg
+    import scipy.sparse as sp
+    from inputs.geometry import merge, random_complex
+    ph = Physics(freq)
+    # internal part: oracle blocks of a few small objects of this workload, GEMVs timed
+    counts = np.bincount(mesh.obj)
+    order = np.argsort(counts)
+    pick = order[len(order) // 2: len(order) // 2 + 3]
+    parts = []
+    for i in pick:
+        sel = np.nonzero(mesh.obj == i)[0]
+        vids, inv = np.unique(mesh.tris[sel], return_inverse=True)
+        parts.append((mesh.verts[vids], inv.reshape(-1, 3).astype(np.int32)))
+    sub = merge(parts)
+    g = build_rwg(sub.verts, sub.tris, sub.obj, sub.n_obj)
+    inner = interior_blocks(g, ph)
+    H = random_complex(g.n_e, 0)
+    reps = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < 3.0:
+        for i in range(g.n_obj):
+            s = slice(g.obj_edge_off[i], g.obj_edge_off[i + 1])
+            inner.Z[i] @ H[s]
+            inner.M[i] @ H[s]
+        reps += 1
+    t_int = (time.perf_counter() - t0) / reps
+    ent_sample = sum(2 * Z.size for Z in inner.Z)
+    ent_all = float(np.sum(2.0 * (1.5 * counts) ** 2))
+    t_internal = t_int * ent_all / ent_sample
+    t_ext = 0.0
+    note = "internal: oracle Z_i, M_i GEMVs of objects %s (%d entries), scaled by entry count" % (
+        list(map(int, pick)), ent_sample)
+    if grid[0] > 0:
+        # grid convolution: one component on a quarter-size grid, scaled by N^3 log N^3, times 4
+        Nq = max(8, grid[0] // 4)
+        gq = Grid(np.array([Nq] * 3), np.array([2e-6] * 3), np.zeros(3))
+        Ghat = np.fft.fftn(circulant_kernel(gq, ph.k0))
+        src = random_complex(Nq ** 3, 1)
+        t0 = time.perf_counter()
+        convolve_fft(gq, Ghat, src)
+        tq = time.perf_counter() - t0
+        scale = (grid[0] / Nq) ** 3 * np.log(grid[0]) / np.log(Nq)
+        t_fft = 4 * tq * scale
+        # near field, projection and interpolation: scipy CSR products (as in the oracle) per non-zero
+        rng = np.random.default_rng(0)
+        nrow = 200000
+        nnz_row = max(1, int(round(lay.nnz_near_A / lay.n_e)))
+        cols = rng.integers(0, nrow, size=nrow * nnz_row)
+        A = sp.csr_matrix((np.ones(cols.size, complex), (np.repeat(np.arange(nrow), nnz_row), cols)), shape=(nrow, nrow))
+        v = random_complex(nrow, 2)
+        t0 = time.perf_counter()
+        A @ v
+        t_nnz = (time.perf_counter() - t0) / A.nnz
+        nnz_total = lay.nnz_near_A + lay.nnz_near_phi + 2 * (81 * lay.n_e + 27 * lay.n_t)
+        t_ext = t_fft + t_nnz * nnz_total
+        note += ("; FFT convolution: oracle on a %d^3 grid scaled by N^3 log N to %d^3, x4 components; "
+                 "near field / P / W: scipy CSR product per non-zero x %d non-zeros" % (Nq, grid[0], nnz_total))
+    total = t_internal + t_ext
+    threads = 1
+    for info in threadpool_info():
+        if info.get("user_api") == "blas":
+            threads = max(threads, int(info.get("num_threads", 1)))
+    return dict(value=1.0 / total, unit="matvecs/s", cores=threads, kind="oracle",
+                sample=note + "; seconds per product: internal %.3g, external %.3g (extrapolated)" % (t_internal, t_ext))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="conductors", choices=sorted(WORKLOADS))
+    ap.add_argument("--solve", action="store_true", help="also time GMRES to 1e-6 (mixed GMRES-IR vs FP64)")
+    ap.add_argument("--solve-max-iter", type=int, default=3000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--sched", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the product is built and applied on a single MI355X "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2108_03991_amd import slim
+    from inputs.geometry import random_complex
+
+    kw, freq, grid = WORKLOADS[args.workload]
+    t0 = time.time()
+    mesh = make_mesh(args.workload, kw)
+    log("mesh: %d triangles, %d objects (%.1f s)" % (mesh.n_tri, mesh.n_obj, time.time() - t0))
+    ctx = slim.Context(0)
+    ctx.set_mesh(mesh.verts, mesh.tris, mesh.obj, mesh.n_obj)
+    t0 = time.time()
+    lay = ctx.build(freq=freq, grid=grid, sched_mode=args.sched)
+    log("build: %.1f s, n_e %d n_t %d nnzA %d nnzP %d tiles %d slots %d" % (
+        time.time() - t0, lay.n_e, lay.n_t, lay.nnz_near_A, lay.nnz_near_phi, lay.n_tiles, lay.slots))
+    n = lay.n_sys
+    x = torch.tensor(random_complex(n, 7), dtype=torch.complex128, device="cuda")
+    y = torch.zeros_like(x)
+    y64 = torch.zeros_like(x)
+    stream = torch.cuda.current_stream()
+
+    def timed(prec, steps):
+        ctx.profile(True)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(steps):
+            ctx.matvec(prec, x, y if prec == slim.SLIM_MIXED else y64)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        stages, calls = ctx.profile_read()
+        ctx.profile(False)
+        return dt, [s / calls for s in stages]
+
+    for _ in range(args.warmup):
+        ctx.matvec(slim.SLIM_MIXED, x, y)
+        ctx.matvec(slim.SLIM_FP64, x, y64)
+    dt_mixed, st_mixed = timed(slim.SLIM_MIXED, args.steps)
+    dt_fp64, st_fp64 = timed(slim.SLIM_FP64, args.steps)
+    log("mixed %.3f ms/matvec, stages %s" % (1e3 * dt_mixed / args.steps, ["%.3f" % s for s in st_mixed]))
+    log("fp64  %.3f ms/matvec, stages %s" % (1e3 * dt_fp64 / args.steps, ["%.3f" % s for s in st_fp64]))
+    # accuracy of the mixed product against the FP64 product, per row block
+    ne = lay.n_e
+    ym, yd = y.cpu().numpy(), y64.cpu().numpy()
+    err = [float(np.linalg.norm(ym[s] - yd[s]) / np.linalg.norm(yd[s])) for s in (slice(0, ne), slice(ne, n))]
+
+    bytes_m = algorithmic_bytes(mesh, lay, True)
+    bytes_d = algorithmic_bytes(mesh, lay, False)
+    t_int = st_mixed[0] * 1e-3
+    achieved = bytes_m["internal"] / t_int
+    result = {
+        "metric": METRIC,
+        "value": args.steps / dt_mixed,
+        "unit": "matvecs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * dt_mixed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64",
+        "data": "synthetic (seeded geometry generator; random complex x)",
+        "config": {
+            "workload": args.workload, "seed": kw.get("seed"), "freq_hz": freq, "aim_grid": list(grid),
+            "n_e": lay.n_e, "n_t": lay.n_t, "n_obj": lay.n_obj, "nnz_near_A": lay.nnz_near_A,
+            "nnz_near_phi": lay.nnz_near_phi, "internal_entries": lay.internal_entries,
+            "tiles": lay.n_tiles, "slots": lay.slots, "build_s": lay.build_seconds,
+        },
+        "fp64": {"value": args.steps / dt_fp64, "unit": "matvecs/s", "ms_per_step": 1e3 * dt_fp64 / args.steps,
+                 "stage_ms": st_fp64},
+        "stage_ms_mixed": {"internal": st_mixed[0], "project": st_mixed[1], "fft": st_mixed[2],
+                           "pulse_rows": st_mixed[3], "rwg_rows": st_mixed[4], "cont_rows": st_mixed[5]},
+        "mixed_vs_fp64_rel_err": {"y1": err[0], "y2": err[1]},
+        "algorithmic_bytes_mixed": bytes_m,
+        "hbm_frac_whole_product": sum(bytes_m.values()) / (dt_mixed / args.steps) / HBM_PEAK,
+        "roofline": {"kernel": "k_internal<mixed> (internal blocks)", "bound": "hbm", "achieved": achieved / 1e9,
+                     "peak": HBM_PEAK / 1e9, "unit": "GB/s", "frac": achieved / HBM_PEAK, "traffic": None},
+    }
+    if args.solve:
+        b = torch.tensor(random_complex(n, 11), dtype=torch.complex128, device="cuda")
+        for name, prec in (("mixed", slim.SLIM_MIXED), ("fp64", slim.SLIM_FP64)):
+            xs = torch.zeros_like(b)
+            info, ok = ctx.solve(b, xs, tol=1e-6, restart=100, max_iter=args.solve_max_iter, prec=prec,
+                                 inner_tol=1e-2, scaled_rhs=True)
+            result["solve_" + name] = {"seconds": info.seconds, "iterations": info.iterations,
+                                       "outer": info.outer_steps, "rel_residual": info.rel_residual,
+                                       "converged": bool(ok)}
+            log("solve %s: %s" % (name, result["solve_" + name]))
+    if not args.no_cpu_baseline:
+        t0 = time.time()
+        result["cpu_baseline"] = cpu_baseline(mesh, lay, freq, grid)
+        log("cpu baseline %.1f s" % (time.time() - t0))
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

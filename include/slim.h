@@ -165,6 +165,20 @@ slim_status slim_matvec_parts(slim_ctx* ctx, slim_prec prec, const void* x_dev, 
 slim_status slim_internal_apply(slim_ctx* ctx, slim_prec prec, const void* H_dev, void* e_dev,
                                 void* g_dev, double* ms, void* stream);
 
+/* AIM pieces on their own, for checks against an independent implementation.
+ * slim_aim_convolve: grid convolution H of eq. (11) of ncomp (1..4) complex128
+ *   source grids (ncomp x Nx Ny Nz, node order x fastest) into potentials.
+ * slim_get_aim: host copies of the stencil centres (3 int32 per basis, node
+ *   index) and weights (RWG: 3 x 27 doubles, component-major; pulse: 27).
+ * slim_get_near: host copy of the near-field CSR of L_A,NR (which = 0,
+ *   n_e rows) or L_phi,NR (which = 1, n_t rows, each column u already scaled by
+ *   A_u): ptr (rows+1 int64), col (nnz int32), val (2 nnz doubles).  Any
+ *   pointer may be NULL. */
+slim_status slim_aim_convolve(slim_ctx* ctx, slim_prec prec, const void* src_dev, void* dst_dev, int32_t ncomp,
+                              void* stream);
+slim_status slim_get_aim(const slim_ctx* ctx, int32_t* cidx_e, double* w_e, int32_t* cidx_t, double* w_t);
+slim_status slim_get_near(const slim_ctx* ctx, int32_t which, int64_t* ptr, int32_t* col, double* val);
+
 /* Right-hand side of (7) for an incident plane wave E0 epol e^{-j k0 khat.r}. */
 slim_status slim_rhs_planewave(slim_ctx* ctx, const double khat[3], const double epol[3],
                                void* b_dev, void* stream);
@@ -175,6 +189,16 @@ slim_status slim_rhs_planewave(slim_ctx* ctx, const double khat[3], const double
  * according to `scaled_rhs` (1: b_dev already equilibrated).  Synchronous. */
 slim_status slim_solve(slim_ctx* ctx, const void* b_dev, int32_t scaled_rhs, void* x_dev,
                        const slim_solve_opts* opts, slim_solve_info* info, void* stream);
+
+/* Per-stage timing of slim_matvec with HIP events recorded on the caller's
+ * stream around each kernel group: 0 internal blocks (A1, A2), 1 projection
+ * P, 2 FFT convolution (all passes), 3 pulse rows (W, L_phi,NR), 4 RWG rows
+ * (W, L_A,NR, combine), 5 continuity rows and casts.  slim_profile(ctx, 1)
+ * clears and starts recording; slim_profile_read synchronizes on the last
+ * recorded event and returns the summed milliseconds per stage (ms[6]) and
+ * the number of matvecs recorded. */
+slim_status slim_profile(slim_ctx* ctx, int32_t on);
+slim_status slim_profile_read(slim_ctx* ctx, double* ms, int64_t* n_matvec);
 
 /* --- internal task scheduling (Alg. 1, Part_Schedule idea; learned cost) ---- */
 /* Record per-tile start/end timestamps on the next internal launches. */

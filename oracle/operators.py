@@ -115,7 +115,9 @@ def triangle_pair_integrals(g: RWG, T, U, k, qp: QuadParams, want_k=True, worker
             s = sel[lo:lo + step]
             jobs.append((s, (V[T[s]], V[U[s]], k, flag, cop[s], qp, want_k)))
     if workers > 1 and len(jobs) > 1:
-        with ProcessPoolExecutor(max_workers=workers) as ex:
+        import multiprocessing
+        # fresh interpreters: the workers never inherit a GPU context of the parent
+        with ProcessPoolExecutor(max_workers=workers, mp_context=multiprocessing.get_context("spawn")) as ex:
             results = list(ex.map(_pair_job, [j[1] for j in jobs]))
     else:
         results = [_pair_job(j[1]) for j in jobs]

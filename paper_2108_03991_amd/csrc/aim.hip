@@ -315,6 +315,10 @@ void build_aim(Ctx& c, hipStream_t s) {
   const GridDef& G = c.grid;
   Stencils SE, ST;
   stencils(c, SE, ST);
+  c.h_cidx_e = SE.cidx;
+  c.h_cidx_t = ST.cidx;
+  c.h_w_e = SE.w;
+  c.h_w_t = ST.w;
 
   // ---- interpolation W (basis-major) ----
   {

@@ -162,6 +162,8 @@ void lu_solve(rocblas_handle h, int n, double* LU, const rocblas_int* ipiv, doub
 }  // namespace
 
 Ctx::~Ctx() {
+  for (auto& v : prof_ev)
+    for (hipEvent_t e : v) (void)hipEventDestroy(e);
   if (ev_fork) (void)hipEventDestroy(ev_fork);
   if (ev_join) (void)hipEventDestroy(ev_join);
   if (s_aux) (void)hipStreamDestroy(s_aux);
@@ -287,6 +289,10 @@ void build_all(Ctx& c, const slim_build_opts& o) {
   auto t_start = std::chrono::steady_clock::now();
   SLIM_REQUIRE(c.has_mesh, SLIM_E_STATE, "slim_set_mesh must be called before slim_build");
   SLIM_REQUIRE(o.freq > 0.0, SLIM_E_ARG, "frequency must be positive");
+  const bool aim = !(o.grid[0] == 0 && o.grid[1] == 0 && o.grid[2] == 0);
+  for (int k = 0; aim && k < 3; ++k)
+    SLIM_REQUIRE(o.grid[k] >= 8 && o.grid[k] <= 512 && (o.grid[k] & (o.grid[k] - 1)) == 0, SLIM_E_UNSUPPORTED,
+                 "AIM grid size must be a power of two between 8 and 512 per axis");
   SLIM_HIP(hipSetDevice(c.device));
   c.built = false;
   c.opts = o;

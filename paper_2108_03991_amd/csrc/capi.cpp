@@ -250,6 +250,80 @@ slim_status slim_solve(slim_ctx* h, const void* b, int32_t scaled_rhs, void* x, 
   });
 }
 
+slim_status slim_aim_convolve(slim_ctx* h, slim_prec prec, const void* src, void* dst, int32_t ncomp, void* stream) {
+  return guard(h, [&]() {
+    SLIM_REQUIRE(h->c.built && !h->c.plain, SLIM_E_STATE, "no AIM operator built");
+    SLIM_REQUIRE(src && dst && ncomp >= 1 && ncomp <= 4, SLIM_E_ARG, "bad arguments");
+    SLIM_HIP(hipSetDevice(h->c.device));
+    hipStream_t s = as_stream(stream);
+    const int64_t n = ncomp * h->c.grid.nodes();
+    const bool f64 = prec == SLIM_FP64;
+    void* in = f64 ? h->c.d_oct_in.p : h->c.d_oct_in32.p;
+    if (f64) SLIM_HIP(hipMemcpyAsync(in, src, size_t(n) * 16, hipMemcpyDeviceToDevice, s));
+    else launch_cast_c128_to_c64(src, in, n, s);
+    aim_convolve(h->c, f64, ncomp, s);
+    if (f64) SLIM_HIP(hipMemcpyAsync(dst, h->c.d_oct_out.p, size_t(n) * 16, hipMemcpyDeviceToDevice, s));
+    else launch_cast_c64_to_c128(h->c.d_oct_out.p, dst, n, s);
+    // the projection buffers must stay zero off the occupied nodes
+    SLIM_HIP(hipMemsetAsync(in, 0, size_t(4 * h->c.grid.nodes()) * (f64 ? 16 : 8), s));
+    SLIM_HIP(hipStreamSynchronize(s));
+    return SLIM_OK;
+  });
+}
+
+slim_status slim_get_aim(const slim_ctx* h, int32_t* ce, double* we, int32_t* ct, double* wt) {
+  if (!h) return SLIM_E_ARG;
+  if (!h->c.built || h->c.plain) return SLIM_E_STATE;
+  if (ce) std::copy(h->c.h_cidx_e.begin(), h->c.h_cidx_e.end(), ce);
+  if (we) std::copy(h->c.h_w_e.begin(), h->c.h_w_e.end(), we);
+  if (ct) std::copy(h->c.h_cidx_t.begin(), h->c.h_cidx_t.end(), ct);
+  if (wt) std::copy(h->c.h_w_t.begin(), h->c.h_w_t.end(), wt);
+  return SLIM_OK;
+}
+
+slim_status slim_get_near(const slim_ctx* hc, int32_t which, int64_t* ptr, int32_t* col, double* val) {
+  if (!hc) return SLIM_E_ARG;
+  slim_ctx* h = const_cast<slim_ctx*>(hc);
+  return guard(h, [&]() {
+    SLIM_REQUIRE(h->c.built && !h->c.plain, SLIM_E_STATE, "no AIM operator built");
+    SLIM_REQUIRE(which == 0 || which == 1, SLIM_E_ARG, "which must be 0 or 1");
+    const int64_t rows = which == 0 ? h->c.rwg.n_e : h->c.rwg.n_t;
+    const int64_t nnz = which == 0 ? h->c.nnz_A : h->c.nnz_P;
+    if (ptr) SLIM_HIP(hipMemcpy(ptr, (which == 0 ? h->c.d_nA_ptr : h->c.d_nP_ptr).p, size_t(rows + 1) * 8, hipMemcpyDeviceToHost));
+    if (col) SLIM_HIP(hipMemcpy(col, (which == 0 ? h->c.d_nA_col : h->c.d_nP_col).p, size_t(nnz) * 4, hipMemcpyDeviceToHost));
+    if (val) SLIM_HIP(hipMemcpy(val, (which == 0 ? h->c.d_nA_v128 : h->c.d_nP_v128).p, size_t(nnz) * 16, hipMemcpyDeviceToHost));
+    return SLIM_OK;
+  });
+}
+
+slim_status slim_profile(slim_ctx* h, int32_t on) {
+  return guard(h, [&]() {
+    h->c.prof_on = on != 0;
+    for (auto& u : h->c.prof_used) u = 0;
+    h->c.prof_calls = 0;
+    return SLIM_OK;
+  });
+}
+
+slim_status slim_profile_read(slim_ctx* h, double* ms, int64_t* n_matvec) {
+  return guard(h, [&]() {
+    SLIM_REQUIRE(ms, SLIM_E_ARG, "null output");
+    for (int st = 0; st < 6; ++st) {
+      double tot = 0.0;
+      const size_t used = h->c.prof_used[st];
+      for (size_t k = 0; k + 1 < used; k += 2) {
+        SLIM_HIP(hipEventSynchronize(h->c.prof_ev[st][k + 1]));
+        float t = 0.f;
+        SLIM_HIP(hipEventElapsedTime(&t, h->c.prof_ev[st][k], h->c.prof_ev[st][k + 1]));
+        tot += t;
+      }
+      ms[st] = tot;
+    }
+    if (n_matvec) *n_matvec = h->c.prof_calls;
+    return SLIM_OK;
+  });
+}
+
 slim_status slim_sched_record(slim_ctx* h, int32_t on) {
   return guard(h, [&]() {
     h->c.record = on != 0;

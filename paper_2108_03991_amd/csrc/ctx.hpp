@@ -84,6 +84,8 @@ struct Ctx {
   // FFT work arrays (4 components)
   DevBuf d_oct_in, d_oct_in32;          // projected sources: complex128 / complex64 (zero off the occupied nodes)
   DevBuf d_oct_out, d_x1, d_x2;         // sized for complex128; complex64 uses the front
+  std::vector<int32_t> h_cidx_e, h_cidx_t;     // stencil centres (host copies)
+  std::vector<double> h_w_e, h_w_t;            // stencil weights (host copies)
   // near field
   DevBuf d_nA_ptr, d_nA_col, d_nA_v128, d_nA_v64;
   DevBuf d_nP_ptr, d_nP_col, d_nP_v128, d_nP_v64;     // columns pre-scaled by A_u
@@ -96,6 +98,13 @@ struct Ctx {
   // ---- graphs ----
   hipStream_t s_aux = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+
+  // ---- per-stage timing ----
+  bool prof_on = false;
+  std::vector<hipEvent_t> prof_ev[6];   // start/end pairs per stage
+  size_t prof_used[6] = {0, 0, 0, 0, 0, 0};
+  int64_t prof_calls = 0;
+  void prof_mark(int stage, hipStream_t s);   // records the next event of the stage
 
   // ---- cost model ----
   std::vector<float> mlp_params;        // trained FP32 parameters (empty: untrained)

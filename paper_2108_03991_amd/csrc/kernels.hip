@@ -415,8 +415,12 @@ void matvec_t(Ctx& c, const void* x, void* y, void* e_out, void* g_out, void* a_
   const char* Xc = reinterpret_cast<const char*>(X);
   const void* rho = Xc + ne * es;
   double2* Y = reinterpret_cast<double2*>(y);
+  if (c.prof_on) c.prof_calls++;
+  auto mark = [&](int st) { if (c.prof_on) c.prof_mark(st, s); };
   // A1 + A2
+  mark(0);
   internal_launch<F64>(c, X, c.d_e.p, c.d_j.p, g_out ? c.d_g.p : nullptr, s);
+  mark(0);
   const double inv_eta0 = 1.0 / eta0();
   if (c.plain) {
     hipLaunchKernelGGL(k_dense_gemv<F64>, dim3(nblk(nt, 4)), dim3(256), 0, s, c.d_Lphi_hi.as<float2>(),
@@ -431,29 +435,39 @@ void matvec_t(Ctx& c, const void* x, void* y, void* e_out, void* g_out, void* a_
   } else {
     const int64_t N3 = c.grid.nodes();
     void* oct_in = F64 ? c.d_oct_in.p : c.d_oct_in32.p;
+    mark(1);
     hipLaunchKernelGGL(k_project<F64>, dim3(nblk(c.n_pe_nodes + c.n_pt_nodes)), dim3(256), 0, s,
                        c.d_pe_node.as<int32_t>(), c.d_pe_ptr.as<int32_t>(), c.d_pe_idx.as<int32_t>(),
                        F64 ? c.d_pe_w64.p : c.d_pe_w32.p, c.n_pe_nodes, c.d_pt_node.as<int32_t>(),
                        c.d_pt_ptr.as<int32_t>(), c.d_pt_idx.as<int32_t>(), F64 ? c.d_pt_w64.p : c.d_pt_w32.p,
                        c.n_pt_nodes, c.d_j.p, rho, oct_in, N3);
     SLIM_HIP(hipGetLastError());
+    mark(1);
+    mark(2);
     aim_convolve(c, F64, 4, s);
+    mark(2);
     const int Nx = c.grid.N[0], NxNy = c.grid.N[0] * c.grid.N[1];
+    mark(3);
     hipLaunchKernelGGL(k_phi<F64>, dim3(nblk(nt, 4)), dim3(256), 0, s, c.d_wt_base.as<int32_t>(),
                        F64 ? c.d_wt_w64.p : c.d_wt_w32.p, c.d_oct_out.p, N3, Nx, NxNy, c.d_nP_ptr.as<int64_t>(),
                        c.d_nP_col.as<int32_t>(), F64 ? c.d_nP_v128.p : c.d_nP_v64.p, rho, c.d_phi.p, nt);
     SLIM_HIP(hipGetLastError());
+    mark(3);
+    mark(4);
     hipLaunchKernelGGL((k_rows_A<F64, true>), dim3(nblk(ne, 4)), dim3(256), 0, s, c.d_we_base.as<int32_t>(),
                        F64 ? c.d_we_w64.p : c.d_we_w32.p, c.d_oct_out.p, N3, Nx, NxNy, c.d_nA_ptr.as<int64_t>(),
                        c.d_nA_col.as<int32_t>(), F64 ? c.d_nA_v128.p : c.d_nA_v64.p, c.d_j.p, nullptr, c.d_phi.p,
                        c.d_e.p, c.d_tplus.as<int32_t>(), c.d_tminus.as<int32_t>(), c.d_len.as<double>(),
                        c.d_ix_col.as<int32_t>(), c.d_ix_val.as<double>(), c.k0, inv_eta0, c.d_a.p, Y, ne);
+    mark(4);
   }
   SLIM_HIP(hipGetLastError());
+  mark(5);
   hipLaunchKernelGGL(k_rows_T<F64>, dim3(nblk(nt)), dim3(256), 0, s, c.d_tri_edge.as<int32_t>(),
                      c.d_tri_sign.as<int8_t>(), c.d_len.as<double>(), c.d_area.as<double>(), c.d_j.p, rho, c.k0,
                      Y + ne, nt);
   SLIM_HIP(hipGetLastError());
+  mark(5);
   auto out = [&](const void* src, void* dst, int64_t n) {
     if (!dst) return;
     hipLaunchKernelGGL(k_copy_out<F64>, dim3(nblk(n)), dim3(256), 0, s, src, reinterpret_cast<double2*>(dst), n);
@@ -503,6 +517,16 @@ void launch_usolve_block(const double* U, int64_t ld, int i0, int nb, double* X,
 void launch_scale(double* M, int64_t n, cd f, hipStream_t s) {
   hipLaunchKernelGGL(k_scale, dim3(nblk(n)), dim3(256), 0, s, reinterpret_cast<double2*>(M), n, f.real(), f.imag());
   SLIM_HIP(hipGetLastError());
+}
+
+void Ctx::prof_mark(int stage, hipStream_t s) {
+  std::vector<hipEvent_t>& v = prof_ev[stage];
+  if (prof_used[stage] == v.size()) {
+    hipEvent_t e;
+    SLIM_HIP(hipEventCreate(&e));
+    v.push_back(e);
+  }
+  SLIM_HIP(hipEventRecord(v[prof_used[stage]++], s));
 }
 
 void matvec(Ctx& c, slim_prec prec, const void* x, void* y, void* e_out, void* g_out, void* a_out, void* phi_out,

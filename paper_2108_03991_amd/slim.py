@@ -89,10 +89,16 @@ def lib():
         L.slim_sched_train.argtypes = [vp, i32, C.c_double, dp]
         L.slim_sched_set_mode.argtypes = [vp, i32]
         L.slim_mlp_forward_backward.argtypes = [i32, i32, vp, vp, vp, vp, vp, vp, vp]
+        L.slim_aim_convolve.argtypes = [vp, i32, vp, vp, i32, vp]
+        L.slim_get_aim.argtypes = [vp, vp, vp, vp, vp]
+        L.slim_get_near.argtypes = [vp, i32, vp, vp, vp]
+        L.slim_profile.argtypes = [vp, i32]
+        L.slim_profile_read.argtypes = [vp, dp, C.POINTER(i64)]
         for name in ("slim_create", "slim_set_mesh", "slim_set_materials", "slim_build", "slim_get_layout",
                      "slim_get_rwg", "slim_matvec", "slim_matvec_parts", "slim_internal_apply",
                      "slim_rhs_planewave", "slim_solve", "slim_sched_record", "slim_sched_tiles",
-                     "slim_sched_train", "slim_sched_set_mode", "slim_mlp_forward_backward"):
+                     "slim_sched_train", "slim_sched_set_mode", "slim_mlp_forward_backward", "slim_profile",
+                     "slim_profile_read", "slim_aim_convolve", "slim_get_aim", "slim_get_near"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -101,7 +107,8 @@ def lib():
 EXPORTS = ["slim_default_build_opts", "slim_create", "slim_destroy", "slim_last_error", "slim_set_mesh",
            "slim_set_materials", "slim_build", "slim_get_layout", "slim_get_rwg", "slim_matvec",
            "slim_matvec_parts", "slim_internal_apply", "slim_rhs_planewave", "slim_solve", "slim_sched_record",
-           "slim_sched_tiles", "slim_sched_train", "slim_sched_set_mode", "slim_mlp_forward_backward"]
+           "slim_sched_tiles", "slim_sched_train", "slim_sched_set_mode", "slim_mlp_forward_backward",
+           "slim_profile", "slim_profile_read", "slim_aim_convolve", "slim_get_aim", "slim_get_near"]
 
 
 def _ptr(t):
@@ -209,6 +216,33 @@ class Context:
         if st not in (0, 7):
             self._check(st)
         return info, st == 0
+
+    def aim_convolve(self, prec, src, dst, ncomp, stream=None):
+        self._check(lib().slim_aim_convolve(self._h, prec, _ptr(src), _ptr(dst), int(ncomp), _stream(stream)))
+
+    def get_aim(self, n_e, n_t):
+        ce = np.zeros(3 * n_e, np.int32)
+        we = np.zeros(81 * n_e)
+        ct = np.zeros(3 * n_t, np.int32)
+        wt = np.zeros(27 * n_t)
+        self._check(lib().slim_get_aim(self._h, ce.ctypes.data, we.ctypes.data, ct.ctypes.data, wt.ctypes.data))
+        return ce.reshape(-1, 3), we.reshape(-1, 3, 27), ct.reshape(-1, 3), wt.reshape(-1, 27)
+
+    def get_near(self, which, rows, nnz):
+        ptr = np.zeros(rows + 1, np.int64)
+        col = np.zeros(nnz, np.int32)
+        val = np.zeros(2 * nnz)
+        self._check(lib().slim_get_near(self._h, int(which), ptr.ctypes.data, col.ctypes.data, val.ctypes.data))
+        return ptr, col, val.view(np.complex128)
+
+    def profile(self, on=True):
+        self._check(lib().slim_profile(self._h, int(bool(on))))
+
+    def profile_read(self):
+        ms = (C.c_double * 6)()
+        n = C.c_int64(0)
+        self._check(lib().slim_profile_read(self._h, ms, C.byref(n)))
+        return list(ms), n.value
 
     def sched_record(self, on=True):
         self._check(lib().slim_sched_record(self._h, int(bool(on))))

@@ -1,0 +1,35 @@
+"""Host-side checks of the C ABI library (no GPU needed)."""
+import ctypes
+import re
+
+import pytest
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2108_03991_amd import slim
+    L = slim.lib()
+    header = open(__file__.replace('tests/test_capi_cpu.py', 'include/slim.h')).read()
+    declared = set(re.findall(r'\b(slim_[a-z_0-9]+)\s*\(', header))
+    assert declared == set(slim.EXPORTS)
+    for name in declared:
+        assert hasattr(L, name)
+
+
+def test_null_arguments_are_rejected():
+    from paper_2108_03991_amd import slim
+    L = slim.lib()
+    assert L.slim_create(0, None) == 1
+    assert L.slim_set_mesh(None, None, 0, None, 0, None, 0) == 1
+    assert L.slim_matvec(None, 0, None, None, None) == 1
+    assert L.slim_build(None, None) == 1
+    assert L.slim_get_layout(None, None) == 1
+    L.slim_destroy(None)
+    assert b"null" in L.slim_last_error(None)
+    assert L.slim_mlp_forward_backward(0, 1, None, None, None, None, None, None, None) == 1
+
+
+def test_default_build_options():
+    from paper_2108_03991_amd import slim
+    o = slim.default_build_opts()
+    assert (o.near_cheb, o.n_far, o.n_near, o.levels, o.n_r, o.n_t) == (3, 4, 5, 3, 5, 6)
+    assert o.q == 0.25 and o.c_near == 2.0

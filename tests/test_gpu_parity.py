@@ -1,0 +1,165 @@
+"""GPU parity of the SLIM system product (eq. (7)-(8)) against the FP64 oracle.
+
+Tolerances (relative 2-norm, per row block and per intermediate vector):
+  FP64 path: the operators are built with the same quadrature rules as the
+  oracle, so e = Z H and phi agree to rounding (1e-11).  Y_eq solves an
+  interior EFIE with cond(L_k0) ~ 1e9 at these sizes: any two FP64 LU solves
+  differ by about cond * eps ~ 1e-7, hence 1e-6 for g = M H and everything
+  that depends on it (a, y).
+  MIXED path: 1e-5, the bound the method sets for complex64 storage and FP32
+  accumulation.
+"""
+import numpy as np
+import pytest
+
+from inputs.geometry import random_complex, small_boxes
+from tests.gpu_util import context, rel, run_parts
+
+pytestmark = pytest.mark.gpu
+
+FP64, MIXED = 0, 1
+
+
+@pytest.fixture(scope="module")
+def c1_gpu(c1_mesh):
+    return context(c1_mesh, freq=10e9, grid=(0, 0, 0))
+
+
+def _oracle_parts(S, x):
+    y, p = S.matvec(x)
+    return dict(y=y, e=p['e'], g=p['g'], a=p['a'], phi=p['phi'])
+
+
+TOL = {FP64: dict(e=1e-11, phi=1e-11, g=1e-6, a=1e-6, y=1e-6), MIXED: dict(e=1e-5, phi=1e-5, g=1e-5, a=1e-5, y=1e-5)}
+
+
+def _check(got, ref, ne, prec):
+    for k in ('e', 'g', 'a', 'phi'):
+        assert rel(got[k], ref[k]) <= TOL[prec][k], (k, rel(got[k], ref[k]))
+    assert rel(got['y'][:ne], ref['y'][:ne]) <= TOL[prec]['y']
+    assert rel(got['y'][ne:], ref['y'][ne:]) <= TOL[prec]['y']
+
+
+@pytest.mark.parametrize("prec", [FP64, MIXED])
+def test_c1_bar_dense_parity(c1_gpu, c1_system, prec):
+    ctx, lay = c1_gpu
+    assert (lay.n_e, lay.n_t) == (888, 592)
+    ev, tp, tm = ctx.rwg(lay.n_e)
+    assert np.array_equal(ev, c1_system.g.edge_v) and np.array_equal(tp, c1_system.g.tplus)
+    for seed in (1, 2):
+        x = random_complex(lay.n_e + lay.n_t, seed)
+        _check(run_parts(ctx, lay, prec, x), _oracle_parts(c1_system, x), lay.n_e, prec)
+
+
+def test_c1_ragged_vectors(c1_gpu, c1_system):
+    """Edge cases of the input vector: zero, only H, only c0 rho."""
+    ctx, lay = c1_gpu
+    ne, n = lay.n_e, lay.n_e + lay.n_t
+    z = run_parts(ctx, lay, FP64, np.zeros(n, complex))
+    assert all(np.all(v == 0) for v in z.values())
+    for part in (slice(0, ne), slice(ne, n)):
+        x = np.zeros(n, complex)
+        x[part] = random_complex(n, 9)[part]
+        got, ref = run_parts(ctx, lay, FP64, x), _oracle_parts(c1_system, x)
+        for rows in (slice(0, ne), slice(ne, n)):
+            if np.linalg.norm(ref['y'][rows]) > 0:
+                assert rel(got['y'][rows], ref['y'][rows]) <= 1e-6
+
+
+def test_repeatable_and_schedule_invariant(c1_mesh):
+    """Bitwise-identical products on repeat and under every packing of the internal tiles
+    (each row is reduced by one wave in a fixed order, so the schedule cannot change it)."""
+    ctx, lay = context(c1_mesh, freq=10e9, grid=(0, 0, 0), tile_rows=16)
+    x = random_complex(lay.n_e + lay.n_t, 3)
+    base = run_parts(ctx, lay, FP64, x)
+    again = run_parts(ctx, lay, FP64, x)
+    assert all(np.array_equal(base[k], again[k]) for k in base)
+    for mode in (2, 0):
+        ctx.sched_set_mode(mode)
+        other = run_parts(ctx, lay, FP64, x)
+        assert all(np.array_equal(base[k], other[k]) for k in base)
+    # a second build (odd slot count, taller tiles): the assembly accumulates with
+    # atomics, so operators of two builds agree to rounding (amplified by the
+    # interior EFIE conditioning), not bit for bit
+    ctx2, lay2 = context(c1_mesh, freq=10e9, grid=(0, 0, 0), tile_rows=64, slots=7)
+    other = run_parts(ctx2, lay2, FP64, x)
+    for k in base:
+        assert rel(other[k], base[k]) <= 1e-6
+
+
+@pytest.fixture(scope="module")
+def boxes_case():
+    """Four small conductors of uneven size with an AIM grid: oracle O-aim."""
+    from oracle import aim
+    from oracle.operators import Physics, interior_blocks
+    from oracle.rwg import build_rwg, matrix_D, matrix_Ix_and_gram
+    m = small_boxes(4, seed=1)
+    g = build_rwg(m.verts, m.tris, m.obj, m.n_obj)
+    ph = Physics(10e9)
+    grid = aim.make_grid(g.verts, (16, 16, 16))
+    op = aim.build_aim(g, grid, ph.k0, lambda a, b: aim.exact_entries(g, ph.k0, a, b),
+                       lambda a, b: aim.exact_phi_entries(g, ph.k0, a, b))
+    Ix, _ = matrix_Ix_and_gram(g)
+    inner = interior_blocks(g, ph, Ix=Ix)
+    return m, g, ph, op, Ix, matrix_D(g), inner
+
+
+def _oracle_aim_parts(case, x):
+    from oracle.operators import ETA0
+    m, g, ph, op, Ix, D, inner = case
+    ne = g.n_e
+    H, crho = x[:ne], x[ne:]
+    e = np.zeros(ne, complex)
+    gg = np.zeros(ne, complex)
+    for i in range(g.n_obj):
+        s = slice(g.obj_edge_off[i], g.obj_edge_off[i + 1])
+        e[s] = inner.Z[i] @ H[s]
+        gg[s] = inner.M[i] @ H[s]
+    j = H - gg
+    a = op.apply_LA(j)
+    phi = op.apply_Lphi(g.area * crho)
+    y1 = 1j * ph.k0 * a + D.T @ phi + Ix @ e / ETA0
+    y2 = -(D @ j) / g.area + 1j * ph.k0 * crho
+    return dict(y=np.concatenate([y1, y2]), e=e, g=gg, a=a, phi=phi)
+
+
+@pytest.mark.parametrize("prec", [FP64, MIXED])
+def test_aim_multi_object_parity(boxes_case, prec):
+    m = boxes_case[0]
+    ctx, lay = context(m, freq=10e9, grid=(16, 16, 16))
+    assert lay.nnz_near_A == boxes_case[3].LA_nr.nnz and lay.nnz_near_phi == boxes_case[3].Lphi_nr.nnz
+    for seed in (4, 5):
+        x = random_complex(lay.n_e + lay.n_t, seed)
+        _check(run_parts(ctx, lay, prec, x), _oracle_aim_parts(boxes_case, x), lay.n_e, prec)
+
+
+def test_mesh_and_state_errors(c1_mesh):
+    from paper_2108_03991_amd import slim
+    ctx = slim.Context(0)
+    with pytest.raises(slim.SlimError) as ei:
+        ctx.set_mesh(c1_mesh.verts, c1_mesh.tris[:-1], c1_mesh.obj[:-1], 1)
+    assert ei.value.code == 2 and "closed" in str(ei.value)
+    bad = c1_mesh.tris.copy()
+    bad[0] = bad[0, ::-1]
+    with pytest.raises(slim.SlimError) as ei:
+        ctx.set_mesh(c1_mesh.verts, bad, c1_mesh.obj, 1)
+    assert ei.value.code == 2
+    with pytest.raises(slim.SlimError) as ei:
+        ctx.set_mesh(c1_mesh.verts, c1_mesh.tris, c1_mesh.obj + 2, 1)
+    assert ei.value.code == 2
+    ctx.set_mesh(c1_mesh.verts, c1_mesh.tris, c1_mesh.obj, 1)
+    import torch
+    x = torch.zeros(1480, dtype=torch.complex128, device='cuda')
+    y = torch.zeros_like(x)
+    with pytest.raises(slim.SlimError) as ei:
+        ctx.matvec(0, x, y)
+    assert ei.value.code == 3
+    with pytest.raises(slim.SlimError) as ei:
+        ctx.build(freq=-1.0)
+    assert ei.value.code == 1
+    with pytest.raises(slim.SlimError) as ei:
+        ctx.build(freq=10e9, grid=(12, 12, 12))       # the FFT needs 2N a power of two
+    assert ei.value.code == 8
+    with pytest.raises(slim.SlimError) as ei:
+        ctx.build(freq=10e9, mem_budget=1000)
+    assert ei.value.code == 4

@@ -1,0 +1,41 @@
+"""GMRES and GMRES-IR through the C ABI vs the oracle's dense LU solution (C1 bar)."""
+import numpy as np
+import pytest
+
+from inputs.geometry import random_complex
+from oracle.solve import lu_solve, row_scaling
+from tests.gpu_util import context
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_gmres_matches_lu(c1_mesh, c1_system, prec):
+    import torch
+    ctx, lay = context(c1_mesh, freq=10e9, grid=(0, 0, 0))
+    S = c1_system
+    s = row_scaling(S.g.n_e, S.g.n_t, np.mean(S.g.length))
+    assert abs(lay.mean_edge / np.mean(S.g.length) - 1) < 1e-14
+    A = s[:, None] * S.dense()
+    r = random_complex(A.shape[0], seed=0)            # right side of the equilibrated system
+    xs = lu_solve(A, r)
+    b = torch.tensor(r, device='cuda')
+    x = torch.zeros_like(b)
+    info, ok = ctx.solve(b, x, tol=1e-8, restart=300, max_iter=6000, prec=prec, inner_tol=1e-3,
+                         scaled_rhs=True)
+    assert ok and info.rel_residual <= 1e-8
+    xg = x.cpu().numpy()
+    cond = np.linalg.cond(A)
+    assert np.linalg.norm(A @ xg - r) <= 1.01e-8 * np.linalg.norm(r) * 10
+    assert np.linalg.norm(xg - xs) / np.linalg.norm(xs) <= 10 * cond * 1e-8
+    if prec == 1:
+        assert info.n_matvec_mixed > info.n_matvec_fp64
+
+
+def test_gmres_not_converged_returns_best_iterate(c1_mesh):
+    import torch
+    ctx, lay = context(c1_mesh, freq=10e9, grid=(0, 0, 0))
+    b = torch.tensor(random_complex(lay.n_sys, 1), device='cuda')
+    x = torch.zeros_like(b)
+    info, ok = ctx.solve(b, x, tol=1e-12, restart=20, max_iter=40, prec=0, scaled_rhs=True)
+    assert not ok and info.iterations == 40 and 0 < info.rel_residual < 1
