@@ -14,6 +14,7 @@
 //  * near zone: stencil centres within Chebyshev index distance near_cheb (3);
 //  * L_NR = exact near entries - sum_c P_c^T G P_c on the near zone.
 #include <algorithm>
+#include <cstdio>
 #include <numeric>
 
 #include "ctx.hpp"
@@ -416,6 +417,10 @@ void build_aim(Ctx& c, hipStream_t s) {
     SLIM_HIP(hipGetLastError());
     SLIM_HIP(hipStreamSynchronize(s));
     (rwg ? c.nnz_A : c.nnz_P) = nnz;
+    if (o.verbose) {
+      std::fprintf(stderr, "[slim build] near field %s: %lld non-zeros\n", rwg ? "L_A" : "L_phi", (long long)nnz);
+      std::fflush(stderr);
+    }
   }
   // ---- Green's function spectrum ----
   fft_init_twiddles(c);

@@ -248,6 +248,15 @@ static void build_internal(Ctx& c, hipStream_t s) {
     launch_pack_block(bufZ.as<double>(), bufL.as<double>(), n, c.d_hi.as<Cplx<float>>() + c.blocks[i].off,
                       c.d_lo.as<Cplx<float>>() + c.blocks[i].off, s);
     SLIM_HIP(hipStreamSynchronize(s));   // the pair list of the next object reuses d_pairs
+    if (c.opts.verbose) {
+      static thread_local auto last = std::chrono::steady_clock::now();
+      auto now = std::chrono::steady_clock::now();
+      if (i + 1 == r.n_obj || std::chrono::duration<double>(now - last).count() > 10.0) {
+        std::fprintf(stderr, "[slim build] interior blocks %d / %d (n = %d)\n", i + 1, r.n_obj, n);
+        std::fflush(stderr);
+        last = now;
+      }
+    }
   }
   std::vector<rocblas_int> h_info(2 * size_t(r.n_obj));
   SLIM_HIP(hipMemcpy(h_info.data(), info.p, info.bytes, hipMemcpyDeviceToHost));
@@ -328,10 +337,19 @@ void build_all(Ctx& c, const slim_build_opts& o) {
   build_ix(c.mesh, r, ixc, ixv);
   up(c.d_ix_col, ixc); up(c.d_ix_val, ixv);
 
+  auto say = [&](const char* what) {
+    if (!o.verbose) return;
+    std::fprintf(stderr, "[slim build] %s (%.1f s)\n", what,
+                 std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count());
+    std::fflush(stderr);
+  };
+  say("geometry uploaded");
   build_internal(c, s);
+  say("interior blocks done");
   c.plain = (o.grid[0] == 0 && o.grid[1] == 0 && o.grid[2] == 0);
   if (c.plain) build_plain_external(c, s);
   else build_aim(c, s);
+  say("external operator done");
 
   // vectors
   const int64_t nsys = r.n_e + r.n_t;
