@@ -67,22 +67,28 @@ template <int R, class T, bool INV> __device__ __forceinline__ void dftR(C2<T>* 
 // One Stockham stage of radix R on every line of the LDS batch (in place through registers).
 // Element j + r L/R of the input feeds output (j/Ns) Ns R + j%Ns + r Ns, after the
 // twiddle e^{-+2 pi i (j%Ns) r / (Ns R)} and an R-point DFT.
+constexpr int kFftThreads = 512;
+
+// LDS layout of a batch: line b, element i at b * (L + L/8) + i + i/8.  The
+// padding element every eight breaks the 64-byte lane stride of the radix-8
+// write phase, which would otherwise hit the same LDS banks.
+template <int L> __device__ __forceinline__ int pidx(int b, int i) { return b * (L + L / 8) + i + (i >> 3); }
+
 template <class T, int L, int R, int ELEMS, bool INV>
-__device__ __forceinline__ void stage(C2<T>* lds, int Ns, const C2<T>* tw) {
+__device__ __forceinline__ void stage(C2<T>* lds, int Ns, const C2<T>* tw) {   // tw: L twiddles in LDS
   constexpr int NB = ELEMS / R;           // butterflies in the batch
-  constexpr int PER = NB / 256;           // per thread
-  static_assert(NB % 256 == 0, "batch too small");
+  constexpr int PER = NB / kFftThreads;   // per thread
+  static_assert(NB % kFftThreads == 0, "batch too small");
   C2<T> v[PER][R];
   int outb[PER];
 #pragma unroll
   for (int p = 0; p < PER; ++p) {
-    const int it = threadIdx.x + p * 256;
+    const int it = threadIdx.x + p * kFftThreads;
     const int line = it / (L / R), j = it % (L / R);
-    C2<T>* base = lds + line * L;
     const int k = j % Ns;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      C2<T> x = base[j + r * (L / R)];
+      C2<T> x = lds[pidx<L>(line, j + r * (L / R))];
       if (r > 0 && Ns > 1) {
         // twiddle index k r L/(Ns R) in [0, L)
         C2<T> w = tw[(k * r * (L / (Ns * R))) % L];
@@ -92,13 +98,13 @@ __device__ __forceinline__ void stage(C2<T>* lds, int Ns, const C2<T>* tw) {
       v[p][r] = x;
     }
     dftR<R, T, INV>(v[p]);
-    outb[p] = line * L + (j / Ns) * Ns * R + k;
+    outb[p] = (line << 16) | ((j / Ns) * Ns * R + k);
   }
   __syncthreads();
 #pragma unroll
   for (int p = 0; p < PER; ++p)
 #pragma unroll
-    for (int r = 0; r < R; ++r) lds[outb[p] + r * Ns] = v[p][r];
+    for (int r = 0; r < R; ++r) lds[pidx<L>(outb[p] >> 16, (outb[p] & 0xffff) + r * Ns)] = v[p][r];
   __syncthreads();
 }
 
@@ -126,56 +132,66 @@ struct PassArgs {
 // CONTIG: lines are contiguous (in_e == 1), batch = consecutive lines along o1;
 // otherwise the batch is W = ELEMS/L adjacent lines (o1 stride 1) for coalescing.
 template <class T, int L, bool CONTIG, int MODE>
-__global__ void __launch_bounds__(256) k_fft_pass(PassArgs a) {
+__global__ void __launch_bounds__(kFftThreads) k_fft_pass(PassArgs a) {
   constexpr int ELEMS = sizeof(T) == 4 ? 8192 : 4096;
   constexpr int W = ELEMS / L;
   extern __shared__ unsigned char smem_raw[];
   C2<T>* lds = reinterpret_cast<C2<T>*>(smem_raw);
-  const C2<T>* tw = reinterpret_cast<const C2<T>*>(a.tw);
+  C2<T>* tw = lds + (ELEMS / L) * (L + L / 8);
+  for (int e = threadIdx.x; e < L; e += kFftThreads) tw[e] = reinterpret_cast<const C2<T>*>(a.tw)[e];
   const C2<T>* in = reinterpret_cast<const C2<T>*>(a.in) + blockIdx.z * a.comp_in;
   C2<T>* out = reinterpret_cast<C2<T>*>(a.out) + blockIdx.z * a.comp_out;
   const int g1 = blockIdx.x * W;     // first line along o1
   const int o2 = blockIdx.y;
   // load
-  for (int e = threadIdx.x; e < ELEMS; e += 256) {
+  for (int e = threadIdx.x; e < ELEMS; e += kFftThreads) {
     int b, i;
     if (CONTIG) { b = e / L; i = e % L; } else { b = e % W; i = e / W; }
     const int o1 = g1 + b;
     C2<T> v = {T(0), T(0)};
     if (o1 < a.n1 && i < a.n_in) v = in[o1 * a.in_o1 + o2 * a.in_o2 + int64_t(i) * a.in_e];
-    lds[b * L + i] = v;
+    lds[pidx<L>(b, i)] = v;
   }
   __syncthreads();
   if (MODE == 1) fft_batch<T, L, ELEMS, true>(lds, tw);
   else fft_batch<T, L, ELEMS, false>(lds, tw);
   if (MODE == 2) {
     const C2<T>* G = reinterpret_cast<const C2<T>*>(a.mul);
-    for (int e = threadIdx.x; e < ELEMS; e += 256) {
+    for (int e = threadIdx.x; e < ELEMS; e += kFftThreads) {
       int b, i;
       if (CONTIG) { b = e / L; i = e % L; } else { b = e % W; i = e / W; }
       const int o1 = g1 + b;
-      if (o1 < a.n1) lds[b * L + i] = cmul(lds[b * L + i], G[o1 * a.mul_o1 + o2 * a.mul_o2 + int64_t(i) * a.mul_e]);
+      if (o1 < a.n1) lds[pidx<L>(b, i)] = cmul(lds[pidx<L>(b, i)], G[o1 * a.mul_o1 + o2 * a.mul_o2 + int64_t(i) * a.mul_e]);
     }
     __syncthreads();
     fft_batch<T, L, ELEMS, true>(lds, tw);
   }
-  for (int e = threadIdx.x; e < ELEMS; e += 256) {
+  for (int e = threadIdx.x; e < ELEMS; e += kFftThreads) {
     int b, i;
     if (CONTIG) { b = e / L; i = e % L; } else { b = e % W; i = e / W; }
     const int o1 = g1 + b;
-    if (o1 < a.n1 && i < a.n_out) out[o1 * a.out_o1 + o2 * a.out_o2 + int64_t(i) * a.out_e] = lds[b * L + i];
+    if (o1 < a.n1 && i < a.n_out) out[o1 * a.out_o1 + o2 * a.out_o2 + int64_t(i) * a.out_e] = lds[pidx<L>(b, i)];
   }
 }
 
 template <class T, bool CONTIG, int MODE>
 void launch_pass_L(int L, const PassArgs& a, int ncomp, hipStream_t s) {
   constexpr int ELEMS = sizeof(T) == 4 ? 8192 : 4096;
-  const size_t shm = size_t(ELEMS) * sizeof(C2<T>);
+  const size_t shm = size_t(ELEMS + ELEMS / 8 + L) * sizeof(C2<T>);
   const int W = ELEMS / L;
   dim3 grid(unsigned((a.n1 + W - 1) / W), unsigned(a.n2), unsigned(ncomp));
   switch (L) {
-#define SLIM_FFT_CASE(LL)                                                                          \
-  case LL: hipLaunchKernelGGL((k_fft_pass<T, LL, CONTIG, MODE>), grid, dim3(256), shm, s, a); break;
+#define SLIM_FFT_CASE(LL)                                                                                   \
+  case LL: {                                                                                                  \
+    static bool attr_set = false;                                                                             \
+    if (!attr_set) { /* more than 64 KB of dynamic LDS needs the explicit limit */                            \
+      SLIM_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fft_pass<T, LL, CONTIG, MODE>),           \
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, int(shm)));                     \
+      attr_set = true;                                                                                        \
+    }                                                                                                         \
+    hipLaunchKernelGGL((k_fft_pass<T, LL, CONTIG, MODE>), grid, dim3(kFftThreads), shm, s, a);                \
+    break;                                                                                                    \
+  }
     SLIM_FFT_CASE(16) SLIM_FFT_CASE(32) SLIM_FFT_CASE(64) SLIM_FFT_CASE(128) SLIM_FFT_CASE(256)
     SLIM_FFT_CASE(512) SLIM_FFT_CASE(1024)
 #undef SLIM_FFT_CASE

@@ -131,11 +131,19 @@ __global__ void __launch_bounds__(256) k_usolve_block(const double2* U, int64_t 
 
 // ---------------------------------------------------------------------------
 // A1 + A2: persistent internal GEMV over the slot queues, fused epilogue.
-// Each workgroup is one slot; it walks its tiles in order.  A wave takes four
-// consecutive rows at a time and streams them with 16-byte loads (two complex
-// per lane), sharing the H loads between the four rows.
+// Each workgroup is one slot; it walks its tiles in order.  A wave takes eight
+// consecutive rows at a time and streams them with 16-byte non-temporal loads
+// (two complex per lane, two 128-column chunks per iteration: 16 loads in
+// flight per lane), sharing the H loads (L2-resident) between the eight rows.
 // ---------------------------------------------------------------------------
 struct BlockDev { int64_t off; int32_t n; int32_t e0; };
+
+typedef float f4v __attribute__((ext_vector_type(4)));
+// 16-byte streaming load of two complex64 values, marked non-temporal (read once)
+__device__ __forceinline__ float4 ntload(const float2* p) {
+  const f4v v = __builtin_nontemporal_load(reinterpret_cast<const f4v*>(p));
+  return make_float4(v.x, v.y, v.z, v.w);
+}
 
 template <bool F64>
 __global__ void __launch_bounds__(256) k_internal(const float2* __restrict__ hi, const float2* __restrict__ lo,
@@ -144,6 +152,7 @@ __global__ void __launch_bounds__(256) k_internal(const float2* __restrict__ hi,
                                                   void* __restrict__ ev, void* __restrict__ jv, void* __restrict__ gv,
                                                   unsigned long long* __restrict__ stamps) {
   using T = typename P<F64>::T;
+  constexpr int RW = F64 ? 4 : 8;    // rows per wave per sweep (hi + lo doubles the loads in FP64)
   const C2<T>* H = reinterpret_cast<const C2<T>*>(Hv);
   C2<T>* e = reinterpret_cast<C2<T>*>(ev);
   C2<T>* jo = reinterpret_cast<C2<T>*>(jv);
@@ -157,29 +166,59 @@ __global__ void __launch_bounds__(256) k_internal(const float2* __restrict__ hi,
     const BlockDev B = blocks[tl.x];
     const int n = B.n, ld = (n + 1) & ~1;
     const C2<T>* Hs = H + B.e0;
-    for (int r0 = tl.y + 4 * wave; r0 < tl.y + tl.z; r0 += 16) {
-      T ar[4] = {0, 0, 0, 0}, ai[4] = {0, 0, 0, 0};
-      const int nr = min(4, tl.y + tl.z - r0);
-      for (int col = 2 * lane; col < ld; col += 128) {
-        C2<T> h0 = Hs[col], h1 = (col + 1 < n) ? Hs[col + 1] : cz<T>();
-        if (col >= n) h0 = cz<T>();
+    const int rend = tl.y + tl.z;
+    for (int r0 = tl.y + RW * wave; r0 < rend; r0 += 4 * RW) {
+      T ar[RW], ai[RW];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+      for (int q = 0; q < RW; ++q) { ar[q] = 0; ai[q] = 0; }
+      const int nr = min(RW, rend - r0);
+      const int64_t base = B.off + int64_t(r0) * ld;
+      // two column chunks of 128 per iteration: 2 x RW 16-byte loads in flight per lane
+      for (int col = 2 * lane; col < ld; col += 256) {
+        const int col2 = col + 128;
+        C2<T> h0 = cz<T>(), h1 = cz<T>(), h2 = cz<T>(), h3 = cz<T>();
+        if (col < n) h0 = Hs[col];
+        if (col + 1 < n) h1 = Hs[col + 1];
+        if (col2 < n) h2 = Hs[col2];
+        if (col2 + 1 < n) h3 = Hs[col2 + 1];
+        float4 a[RW], b[RW];
+#pragma unroll
+        for (int q = 0; q < RW; ++q) {
+          a[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+          b[q] = make_float4(0.f, 0.f, 0.f, 0.f);
           if (q < nr) {
-            const int64_t idx = B.off + int64_t(r0 + q) * ld + col;
-            float4 a = *reinterpret_cast<const float4*>(hi + idx);
-            T a0r = a.x, a0i = a.y, a1r = a.z, a1i = a.w;
-            if (F64) {
-              float4 b = *reinterpret_cast<const float4*>(lo + idx);
-              a0r += T(b.x); a0i += T(b.y); a1r += T(b.z); a1i += T(b.w);
-            }
-            ar[q] += a0r * h0.x - a0i * h0.y + a1r * h1.x - a1i * h1.y;
-            ai[q] += a0r * h0.y + a0i * h0.x + a1r * h1.y + a1i * h1.x;
+            a[q] = ntload(hi + base + int64_t(q) * ld + col);
+            if (col2 < ld)
+              b[q] = ntload(hi + base + int64_t(q) * ld + col2);
           }
+        }
+        float4 al[RW], bl[RW];
+        if (F64) {
+#pragma unroll
+          for (int q = 0; q < RW; ++q) {
+            al[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+            bl[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (q < nr) {
+              al[q] = ntload(lo + base + int64_t(q) * ld + col);
+              if (col2 < ld)
+                bl[q] = ntload(lo + base + int64_t(q) * ld + col2);
+            }
+          }
+        }
+#pragma unroll
+        for (int q = 0; q < RW; ++q) {
+          T a0r = a[q].x, a0i = a[q].y, a1r = a[q].z, a1i = a[q].w;
+          T b0r = b[q].x, b0i = b[q].y, b1r = b[q].z, b1i = b[q].w;
+          if (F64) {
+            a0r += T(al[q].x); a0i += T(al[q].y); a1r += T(al[q].z); a1i += T(al[q].w);
+            b0r += T(bl[q].x); b0i += T(bl[q].y); b1r += T(bl[q].z); b1i += T(bl[q].w);
+          }
+          ar[q] += a0r * h0.x - a0i * h0.y + a1r * h1.x - a1i * h1.y + b0r * h2.x - b0i * h2.y + b1r * h3.x - b1i * h3.y;
+          ai[q] += a0r * h0.y + a0i * h0.x + a1r * h1.y + a1i * h1.x + b0r * h2.y + b0i * h2.x + b1r * h3.y + b1i * h3.x;
         }
       }
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
+      for (int q = 0; q < RW; ++q) {
         T sr = wave_sum(ar[q]), si = wave_sum(ai[q]);
         if (lane == 0 && q < nr) {
           const int row = r0 + q;

@@ -28,7 +28,7 @@ void pack_tiles(Ctx& c, int mode) {
     int cus = 256;
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, c.device) == hipSuccess && prop.multiProcessorCount > 0) cus = prop.multiProcessorCount;
-    c.slots = c.opts.slots > 0 ? c.opts.slots : 2 * cus;
+    c.slots = c.opts.slots > 0 ? c.opts.slots : 4 * cus;
   }
   const int S = c.slots;
   struct Task { int block, row0, rows; double cost; };

@@ -65,6 +65,14 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError("libslim.so is not built (run __graft_entry__.build()); there is no fallback")
+        # PyTorch ships its own HIP runtime (same SONAMEs as /opt/rocm).  Importing it
+        # first makes the dynamic loader bind libslim to that already-loaded runtime, so
+        # the process has one HIP runtime and torch's streams and allocations are the
+        # library's too.  Loading libslim first would bring in a second runtime.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = C.CDLL(LIB_PATH)
         vp, i32, i64, dp = C.c_void_p, C.c_int32, C.c_int64, C.POINTER(C.c_double)
         L.slim_create.argtypes = [i32, C.POINTER(vp)]

@@ -33,3 +33,14 @@ def test_default_build_options():
     o = slim.default_build_opts()
     assert (o.near_cheb, o.n_far, o.n_near, o.levels, o.n_r, o.n_t) == (3, 4, 5, 3, 5, 6)
     assert o.q == 0.25 and o.c_near == 2.0
+
+
+def test_single_hip_runtime_in_process():
+    """libslim binds to the HIP runtime PyTorch already loaded (same SONAMEs), so torch's
+    streams and allocations are the library's own: exactly one libamdhip64 is mapped."""
+    from paper_2108_03991_amd import slim
+    slim.lib()
+    maps = open('/proc/self/maps').read().splitlines()
+    hip = {line.split()[-1] for line in maps if 'libamdhip64' in line}
+    hsa = {line.split()[-1] for line in maps if 'libhsa-runtime64' in line}
+    assert len(hip) == 1 and len(hsa) == 1, (hip, hsa)
