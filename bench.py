@@ -130,6 +130,41 @@ def cpu_baseline(mesh, lay, freq, grid):
                 sample=note + "; seconds per product: internal %.3g, external %.3g (extrapolated)" % (t_internal, t_ext))
 
 
+def sched_study(ctx, lay, x, reps=7, epochs=3000):
+    """Makespan of the persistent internal kernel (HIP events) under three packings of the
+    same tiles: naive (mesh order, round robin), LPT on flop counts, LPT on times predicted
+    by the cost-model network trained on the GPU from this run's own per-tile timestamps."""
+    import torch
+    from paper_2108_03991_amd import slim
+    H = x[:lay.n_e].contiguous()
+
+    def makespan():
+        ts = [ctx.internal_apply(slim.SLIM_MIXED, H, timed=True) for _ in range(reps)]
+        return float(np.median(ts))
+
+    out = {}
+    ctx.sched_set_mode(0)
+    ctx.sched_record(True)
+    ctx.internal_apply(slim.SLIM_MIXED, H, timed=True)
+    tiles = ctx.sched_tiles()
+    ctx.sched_record(False)
+    dur = tiles[:, 6] - tiles[:, 5]
+    slots = int(tiles[:, 4].max()) + 1
+    busy = np.bincount(tiles[:, 4].astype(int), weights=dur, minlength=slots)
+    out["recorded_tiles"] = int(len(tiles))
+    out["ideal_over_lpt_busy"] = float(dur.sum() / slots / busy.max())
+    t0 = time.time()
+    out["train_loss"] = ctx.sched_train(epochs=epochs, lr=3e-3)
+    out["train_s"] = time.time() - t0
+    for name, mode in (("naive_ms", 2), ("lpt_ms", 0), ("mlp_ms", 1)):
+        ctx.sched_set_mode(mode)
+        makespan()
+        out[name] = makespan()
+    ctx.sched_set_mode(0)
+    out["mlp_gain_vs_lpt"] = out["lpt_ms"] / out["mlp_ms"] - 1.0
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -140,12 +175,25 @@ def main():
     ap.add_argument("--solve-max-iter", type=int, default=3000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sched", type=int, default=0)
+    ap.add_argument("--copy-probe", type=float, default=0.0,
+                    help="only run a plain device copy of this many GiB (HBM counter calibration) and exit")
+    ap.add_argument("--no-sched-study", action="store_true",
+                    help="skip the makespan study (naive / LPT / trained cost model)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the product is built and applied on a single MI355X "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
     import torch
+    if args.copy_probe > 0:
+        n = int(args.copy_probe * 2 ** 30) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log("copy probe: 5 copies of %d bytes" % (4 * n))
+        return
     from paper_2108_03991_amd import slim
     from inputs.geometry import random_complex
 
@@ -182,6 +230,16 @@ def main():
         ctx.matvec(slim.SLIM_FP64, x, y64)
     dt_mixed, st_mixed = timed(slim.SLIM_MIXED, args.steps)
     dt_fp64, st_fp64 = timed(slim.SLIM_FP64, args.steps)
+    # the same products replayed from captured hipGraphs (no per-stage events)
+    graph_rate = {}
+    for name, prec, out in (("mixed", slim.SLIM_MIXED, y), ("fp64", slim.SLIM_FP64, y64)):
+        ctx.matvec(prec, x, out)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(args.steps):
+            ctx.matvec(prec, x, out)
+        torch.cuda.synchronize()
+        graph_rate[name] = args.steps / (time.perf_counter() - t)
     log("mixed %.3f ms/matvec, stages %s" % (1e3 * dt_mixed / args.steps, ["%.3f" % s for s in st_mixed]))
     log("fp64  %.3f ms/matvec, stages %s" % (1e3 * dt_fp64 / args.steps, ["%.3f" % s for s in st_fp64]))
     # accuracy of the mixed product against the FP64 product, per row block
@@ -217,11 +275,15 @@ def main():
         "stage_ms_mixed": {"internal": st_mixed[0], "project": st_mixed[1], "fft": st_mixed[2],
                            "pulse_rows": st_mixed[3], "rwg_rows": st_mixed[4], "cont_rows": st_mixed[5]},
         "mixed_vs_fp64_rel_err": {"y1": err[0], "y2": err[1]},
+        "graph_replay_matvecs_per_s": graph_rate,
         "algorithmic_bytes_mixed": bytes_m,
         "hbm_frac_whole_product": sum(bytes_m.values()) / (dt_mixed / args.steps) / HBM_PEAK,
         "roofline": {"kernel": "k_internal<mixed> (internal blocks)", "bound": "hbm", "achieved": achieved / 1e9,
                      "peak": HBM_PEAK / 1e9, "unit": "GB/s", "frac": achieved / HBM_PEAK, "traffic": None},
     }
+    if not args.no_sched_study:
+        result["schedule"] = sched_study(ctx, lay, x)
+        log("schedule study: %s" % result["schedule"])
     if args.solve:
         b = torch.tensor(random_complex(n, 11), dtype=torch.complex128, device="cuda")
         for name, prec in (("mixed", slim.SLIM_MIXED), ("fp64", slim.SLIM_FP64)):

@@ -90,10 +90,13 @@ typedef struct {
   int32_t slots;          /* persistent workgroups of the internal kernel (0 = auto) */
   int64_t mem_budget;     /* bytes of device memory the build may use (0 = no cap)  */
   int32_t verbose;
+  int32_t use_graphs;     /* slim_matvec replays one captured hipGraph per (prec, x, y) */
 } slim_build_opts;
 
 /* Fill `o` with the defaults used by the tests (near_cheb 3, n_far 4, n_near 5,
- * levels 3, q 0.25, n_r 5, n_t 6, c_near 2, LPT, autotuned tiles).            */
+ * levels 3, q 0.25, n_r 5, n_t 6, c_near 2, LPT, autotuned slot count, graphs on).
+ * Autotuning (slots = 0) times the persistent internal kernel for 2, 4 and 8
+ * workgroups per compute unit at build time and keeps the fastest.           */
 void slim_default_build_opts(slim_build_opts* o);
 
 typedef struct {

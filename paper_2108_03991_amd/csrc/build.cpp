@@ -162,6 +162,7 @@ void lu_solve(rocblas_handle h, int n, double* LU, const rocblas_int* ipiv, doub
 }  // namespace
 
 Ctx::~Ctx() {
+  drop_graphs();
   for (auto& v : prof_ev)
     for (hipEvent_t e : v) (void)hipEventDestroy(e);
   if (ev_fork) (void)hipEventDestroy(ev_fork);
@@ -353,6 +354,7 @@ void build_all(Ctx& c, const slim_build_opts& o) {
 
   // vectors
   const int64_t nsys = r.n_e + r.n_t;
+  c.drop_graphs();
   c.d_x64.alloc(size_t(nsys) * 8);
   c.d_y64.alloc(size_t(nsys) * 8);
   c.d_e.alloc(size_t(r.n_e) * 16);
@@ -366,7 +368,29 @@ void build_all(Ctx& c, const slim_build_opts& o) {
 
   c.tile_rows = o.tile_rows > 0 ? o.tile_rows : 64;
   c.sched_mode = o.sched_mode;
-  pack_tiles(c, o.sched_mode);
+  c.drop_graphs();
+  if (o.slots > 0) {
+    c.slots = o.slots;
+    pack_tiles(c, o.sched_mode);
+  } else {
+    // autotune the number of persistent workgroups of the internal kernel
+    int cus = 256;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, c.device) == hipSuccess && prop.multiProcessorCount > 0) cus = prop.multiProcessorCount;
+    SLIM_HIP(hipMemsetAsync(c.d_x64.p, 0, c.d_x64.bytes, s));
+    SLIM_HIP(hipStreamSynchronize(s));
+    int best = 0;
+    double best_ms = 1e300;
+    for (int per_cu : {2, 4, 8}) {
+      c.slots = per_cu * cus;
+      pack_tiles(c, o.sched_mode == 1 ? 0 : o.sched_mode);
+      const double ms = time_internal(c, 3);
+      if (o.verbose) std::fprintf(stderr, "[slim build] autotune: %d slots -> %.3f ms\n", c.slots, ms);
+      if (ms < best_ms) { best_ms = ms; best = c.slots; }
+    }
+    c.slots = best;
+    pack_tiles(c, o.sched_mode == 1 ? 0 : o.sched_mode);
+  }
   SLIM_HIP(hipStreamSynchronize(s));
 
   slim_layout& Lo = c.layout;

@@ -52,6 +52,7 @@ void slim_default_build_opts(slim_build_opts* o) {
   o->tile_rows = 0;
   o->internal_kernel = 0;
   o->slots = 0;
+  o->use_graphs = 1;
 }
 
 slim_status slim_create(int32_t hip_device, slim_ctx** out) {
@@ -162,7 +163,8 @@ slim_status slim_matvec_parts(slim_ctx* h, slim_prec prec, const void* x, void* 
     SLIM_REQUIRE(x && y && x != y, SLIM_E_ARG, "x and y must be distinct device buffers");
     SLIM_REQUIRE(prec == SLIM_FP64 || prec == SLIM_MIXED, SLIM_E_ARG, "unknown precision");
     SLIM_HIP(hipSetDevice(h->c.device));
-    matvec(h->c, prec, x, y, e, g, a, phi, as_stream(stream));
+    if (!e && !g && !a && !phi && h->c.opts.use_graphs && !h->c.prof_on) matvec_graph(h->c, prec, x, y, as_stream(stream));
+    else matvec(h->c, prec, x, y, e, g, a, phi, as_stream(stream));
     return SLIM_OK;
   });
 }

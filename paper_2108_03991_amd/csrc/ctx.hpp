@@ -96,6 +96,9 @@ struct Ctx {
   DevBuf d_e, d_g, d_j, d_a, d_phi;     // sized for complex128
 
   // ---- graphs ----
+  struct GraphKey { int prec; const void* x; void* y; };
+  std::vector<std::pair<GraphKey, hipGraphExec_t>> graphs;
+  void drop_graphs();
   hipStream_t s_aux = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 
@@ -121,6 +124,8 @@ void build_aim(Ctx& c, hipStream_t s);
 void matvec(Ctx& c, slim_prec prec, const void* x, void* y, void* e_out, void* g_out, void* a_out,
             void* phi_out, hipStream_t s);
 void internal_apply(Ctx& c, slim_prec prec, const void* H, void* e, void* g, hipStream_t s, bool h_is_c128);
+void matvec_graph(Ctx& c, slim_prec prec, const void* x, void* y, hipStream_t s);
+double time_internal(Ctx& c, int reps);   // ms per launch of the mixed internal kernel
 void launch_cast_c128_to_c64(const void* in, void* out, int64_t n, hipStream_t s);
 void launch_cast_c64_to_c128(const void* in, void* out, int64_t n, hipStream_t s);
 void launch_pack_block(const double* Zcm, const double* Mcm, int n, Cplx<float>* hi, Cplx<float>* lo, hipStream_t s);

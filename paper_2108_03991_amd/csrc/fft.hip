@@ -69,13 +69,16 @@ template <int R, class T, bool INV> __device__ __forceinline__ void dftR(C2<T>* 
 // twiddle e^{-+2 pi i (j%Ns) r / (Ns R)} and an R-point DFT.
 constexpr int kFftThreads = 512;
 
-// LDS layout of a batch: line b, element i at b * (L + L/8) + i + i/8.  The
-// padding element every eight breaks the 64-byte lane stride of the radix-8
-// write phase, which would otherwise hit the same LDS banks.
-template <int L> __device__ __forceinline__ int pidx(int b, int i) { return b * (L + L / 8) + i + (i >> 3); }
+// LDS layout of a batch: line b, element i at b * LP + i + i/8 with the odd
+// line stride LP = L + L/8 + 1.  The padding element every eight breaks the
+// 64-byte lane stride of the radix-8 write phase; the odd line stride spreads
+// the lanes of the strided passes (consecutive lanes = consecutive lines) over
+// all banks instead of one.
+template <int L> constexpr int line_stride() { return L + L / 8 + 1; }
+template <int L> __device__ __forceinline__ int pidx(int b, int i) { return b * line_stride<L>() + i + (i >> 3); }
 
 template <class T, int L, int R, int ELEMS, bool INV>
-__device__ __forceinline__ void stage(C2<T>* lds, int Ns, const C2<T>* tw) {   // tw: L twiddles in LDS
+__device__ __forceinline__ void stage(C2<T>* lds, int Ns, const C2<T>* tw) {   // tw: the L twiddles
   constexpr int NB = ELEMS / R;           // butterflies in the batch
   constexpr int PER = NB / kFftThreads;   // per thread
   static_assert(NB % kFftThreads == 0, "batch too small");
@@ -137,8 +140,13 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_pass(PassArgs a) {
   constexpr int W = ELEMS / L;
   extern __shared__ unsigned char smem_raw[];
   C2<T>* lds = reinterpret_cast<C2<T>*>(smem_raw);
-  C2<T>* tw = lds + (ELEMS / L) * (L + L / 8);
-  for (int e = threadIdx.x; e < L; e += kFftThreads) tw[e] = reinterpret_cast<const C2<T>*>(a.tw)[e];
+  // complex64: twiddles staged in LDS; complex128: read from the (cached) table so
+  // that two workgroups still fit the 160 KB of LDS of a compute unit
+  constexpr bool TW_LDS = sizeof(T) == 4;
+  C2<T>* tw_lds = lds + (ELEMS / L) * line_stride<L>();
+  if (TW_LDS)
+    for (int e = threadIdx.x; e < L; e += kFftThreads) tw_lds[e] = reinterpret_cast<const C2<T>*>(a.tw)[e];
+  const C2<T>* tw = TW_LDS ? tw_lds : reinterpret_cast<const C2<T>*>(a.tw);
   const C2<T>* in = reinterpret_cast<const C2<T>*>(a.in) + blockIdx.z * a.comp_in;
   C2<T>* out = reinterpret_cast<C2<T>*>(a.out) + blockIdx.z * a.comp_out;
   const int g1 = blockIdx.x * W;     // first line along o1
@@ -177,7 +185,7 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_pass(PassArgs a) {
 template <class T, bool CONTIG, int MODE>
 void launch_pass_L(int L, const PassArgs& a, int ncomp, hipStream_t s) {
   constexpr int ELEMS = sizeof(T) == 4 ? 8192 : 4096;
-  const size_t shm = size_t(ELEMS + ELEMS / 8 + L) * sizeof(C2<T>);
+  const size_t shm = size_t((ELEMS / L) * (L + L / 8 + 1) + (sizeof(T) == 4 ? L : 0)) * sizeof(C2<T>);
   const int W = ELEMS / L;
   dim3 grid(unsigned((a.n1 + W - 1) / W), unsigned(a.n2), unsigned(ncomp));
   switch (L) {

@@ -568,6 +568,54 @@ void Ctx::prof_mark(int stage, hipStream_t s) {
   SLIM_HIP(hipEventRecord(v[prof_used[stage]++], s));
 }
 
+void Ctx::drop_graphs() {
+  for (auto& g : graphs) (void)hipGraphExecDestroy(g.second);
+  graphs.clear();
+}
+
+// The whole product captured once per (precision, x, y) on the library's stream
+// and replayed on the caller's stream.  Capturing records only kernel launches.
+void matvec_graph(Ctx& c, slim_prec prec, const void* x, void* y, hipStream_t s) {
+  hipGraphExec_t exec = nullptr;
+  for (auto& g : c.graphs)
+    if (g.first.prec == int(prec) && g.first.x == x && g.first.y == y) exec = g.second;
+  if (!exec) {
+    hipGraph_t graph = nullptr;
+    SLIM_HIP(hipStreamBeginCapture(c.s_aux, hipStreamCaptureModeThreadLocal));
+    try {
+      matvec(c, prec, x, y, nullptr, nullptr, nullptr, nullptr, c.s_aux);
+    } catch (...) {
+      (void)hipStreamEndCapture(c.s_aux, &graph);
+      if (graph) (void)hipGraphDestroy(graph);
+      throw;
+    }
+    SLIM_HIP(hipStreamEndCapture(c.s_aux, &graph));
+    hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    SLIM_HIP(e);
+    if (c.graphs.size() >= 8) c.drop_graphs();
+    c.graphs.push_back({Ctx::GraphKey{int(prec), x, y}, exec});
+  }
+  SLIM_HIP(hipGraphLaunch(exec, s));
+}
+
+double time_internal(Ctx& c, int reps) {
+  hipStream_t s = c.s_aux;
+  hipEvent_t a, b;
+  SLIM_HIP(hipEventCreate(&a));
+  SLIM_HIP(hipEventCreate(&b));
+  internal_launch<false>(c, c.d_x64.p, c.d_e.p, c.d_j.p, nullptr, s);
+  SLIM_HIP(hipEventRecord(a, s));
+  for (int r = 0; r < reps; ++r) internal_launch<false>(c, c.d_x64.p, c.d_e.p, c.d_j.p, nullptr, s);
+  SLIM_HIP(hipEventRecord(b, s));
+  SLIM_HIP(hipEventSynchronize(b));
+  float ms = 0.f;
+  SLIM_HIP(hipEventElapsedTime(&ms, a, b));
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  return double(ms) / reps;
+}
+
 void matvec(Ctx& c, slim_prec prec, const void* x, void* y, void* e_out, void* g_out, void* a_out, void* phi_out,
             hipStream_t s) {
   if (prec == SLIM_FP64) matvec_t<true>(c, x, y, e_out, g_out, a_out, phi_out, s);

@@ -8,7 +8,9 @@
 // [Z_i; M_i].  A block is split into P_i panels so that no panel exceeds a
 // quarter of the ideal per-slot load (the moldable step), then all panels are
 // placed by LPT on their estimated time:
-//   mode 0: flop-count estimate rows * n (the LPT fallback),
+//   mode 0: flop-count estimate of the kernel as written: rows rounded up to the
+//           eight-row wave sweep times the row length rounded up to the 256-column
+//           chunk, since lanes past the end of a short row idle (the LPT fallback),
 //   mode 1: time predicted by the trained cost-model network,
 //   mode 2: naive -- objects in mesh order, round robin, one panel height.
 #include <algorithm>
@@ -23,13 +25,9 @@ float mlp_predict_host(const Ctx& c, const float* feat);   // mlp.hip
 void tile_features(const Ctx& c, int block, int rows, float* feat);
 
 void pack_tiles(Ctx& c, int mode) {
+  c.drop_graphs();   // captured products point at the old queues
   const int nb = int(c.blocks.size());
-  if (c.slots <= 0) {
-    int cus = 256;
-    hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, c.device) == hipSuccess && prop.multiProcessorCount > 0) cus = prop.multiProcessorCount;
-    c.slots = c.opts.slots > 0 ? c.opts.slots : 4 * cus;
-  }
+  SLIM_REQUIRE(c.slots > 0, SLIM_E_STATE, "slot count not set");
   const int S = c.slots;
   struct Task { int block, row0, rows; double cost; };
   std::vector<Task> tasks;
@@ -60,7 +58,7 @@ void pack_tiles(Ctx& c, int mode) {
       R = std::min(rows, ((R + 3) / 4) * 4);
       for (int r0 = 0; r0 < rows; r0 += R) {
         const int rr = std::min(R, rows - r0);
-        double cost = double(rr) * ld;
+        double cost = double((rr + 7) / 8 * 8) * double((ld + 255) / 256 * 256);
         if (mode == 1 && !c.mlp_params.empty()) {
           float f[8];
           tile_features(c, i, rr, f);

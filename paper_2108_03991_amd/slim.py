@@ -31,7 +31,7 @@ class BuildOpts(C.Structure):
                 ("n_far", C.c_int32), ("n_near", C.c_int32), ("levels", C.c_int32), ("n_r", C.c_int32),
                 ("n_t", C.c_int32), ("q", C.c_double), ("c_near", C.c_double), ("sched_mode", C.c_int32),
                 ("tile_rows", C.c_int32), ("internal_kernel", C.c_int32), ("slots", C.c_int32),
-                ("mem_budget", C.c_int64), ("verbose", C.c_int32)]
+                ("mem_budget", C.c_int64), ("verbose", C.c_int32), ("use_graphs", C.c_int32)]
 
 
 class Layout(C.Structure):

@@ -184,3 +184,27 @@ def test_grid_convolution_parity(N):
     for prec, tol in ((FP64, 1e-12), (MIXED, 1e-5)):
         ctx.aim_convolve(prec, torch.tensor(src, device='cuda'), dst, 4)
         assert rel(dst.cpu().numpy(), ref) <= tol
+
+
+def test_graph_replay_matches_eager(boxes_case):
+    """slim_matvec replays a captured hipGraph; several replays, with eager products and
+    synchronisations in between, all match the eager product bit for bit."""
+    import torch
+    m = boxes_case[0]
+    ctx, lay = context(m, freq=10e9, grid=(16, 16, 16))
+    x = random_complex(lay.n_sys, 12)
+    for prec in (FP64, MIXED):
+        eager = run_parts(ctx, lay, prec, x)['y']
+        xt = torch.tensor(x, device='cuda')
+        y = torch.zeros_like(xt)
+        for rep in range(4):
+            y.zero_()
+            ctx.matvec(prec, xt, y)
+            torch.cuda.synchronize()
+            assert np.array_equal(y.cpu().numpy(), eager), rep
+            run_parts(ctx, lay, 1 - prec, random_complex(lay.n_sys, rep))   # unrelated eager work
+        ctx.sched_set_mode(2)                                                # repack: graph re-captured
+        ctx.matvec(prec, xt, y)
+        torch.cuda.synchronize()
+        assert np.array_equal(y.cpu().numpy(), eager)
+        ctx.sched_set_mode(0)
