@@ -15,7 +15,8 @@ function names the passage it follows.  Modules:
                and the system product of (7)-(8)
     aim        AIM decomposition (11): stencils P, grid convolution H, W = P^T,
                precorrected near field L_NR
-    solve      dense LU solve and FP64 GMRES of (7)
+    solve      dense LU solve, FP64 GMRES and flexible GMRES of (7)
+    precond    conductor-block (block Jacobi / restricted additive Schwarz) preconditioner
     sched      LPT (Alg. 1, bound (13)), modified Part_Schedule (Alg. 2, (14))
     mlp        FP64 reference of the scheduler's cost-model network
 """
