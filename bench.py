@@ -4,7 +4,7 @@ One step = one full product y = A x of eq. (7)-(8) (internal blocks, AIM
 projection, FFT convolution, interpolation, near field, sparse combine) on the
 seeded synthetic workload, inputs resident in HBM.  Prints one JSON line.
 
-    python bench.py [--steps K] [--warmup W] [--workload conductors] [--solve]
+    python bench.py [--steps K] [--warmup W] [--workload conductors] [--no-solve]
 """
 from __future__ import annotations
 
@@ -165,14 +165,46 @@ def sched_study(ctx, lay, x, reps=7, epochs=3000):
     return out
 
 
+def solve_study(ctx, lay, max_iter):
+    """GMRES time-to-1e-6 for a plane wave, FP64 and mixed (GMRES-IR), right-preconditioned
+    by the conductor blocks; plus how far unpreconditioned GMRES gets in a bounded run."""
+    import torch
+    from paper_2108_03991_amd import slim
+    n = lay.n_sys
+    b = torch.zeros(n, dtype=torch.complex128, device="cuda")
+    ctx.rhs_planewave((0.0, 0.0, -1.0), (1.0, 0.0, 0.0), b)
+    out = {"rhs": "plane wave, E0 = 1 V/m along x, travelling along -z", "tol": 1e-6, "restart": 50,
+           "precond": {"blocks": lay.precond_blocks, "entries": lay.precond_entries, "cap": lay.precond_cap}}
+    sols = {}
+    for name, prec in (("mixed", slim.SLIM_MIXED), ("fp64", slim.SLIM_FP64)):
+        xs = torch.zeros_like(b)
+        torch.cuda.synchronize()
+        info, ok = ctx.solve(b, xs, tol=1e-6, restart=50, max_iter=max_iter, prec=prec, inner_tol=1e-2)
+        out[name] = {"seconds": info.seconds, "iterations": info.iterations, "outer": info.outer_steps,
+                     "precond_applies": info.n_precond, "matvecs_mixed": info.n_matvec_mixed,
+                     "matvecs_fp64": info.n_matvec_fp64, "rel_residual": info.rel_residual, "converged": bool(ok)}
+        sols[name] = xs
+        log("solve %s: %s" % (name, out[name]))
+    out["mixed_vs_fp64_solution_rel_diff"] = float(torch.linalg.norm(sols["mixed"] - sols["fp64"]) /
+                                                   torch.linalg.norm(sols["fp64"]))
+    xs = torch.zeros_like(b)
+    info, ok = ctx.solve(b, xs, tol=1e-6, restart=50, max_iter=200, prec=slim.SLIM_MIXED, inner_tol=1e-2,
+                         use_precond=False)
+    out["unpreconditioned_mixed_200_iterations"] = {"rel_residual": info.rel_residual, "seconds": info.seconds,
+                                                    "converged": bool(ok)}
+    log("solve without preconditioner (200 iterations): %s" % out["unpreconditioned_mixed_200_iterations"])
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="conductors", choices=sorted(WORKLOADS))
-    ap.add_argument("--solve", action="store_true", help="also time GMRES to 1e-6 (mixed GMRES-IR vs FP64)")
-    ap.add_argument("--solve-max-iter", type=int, default=3000)
+    ap.add_argument("--no-solve", action="store_true",
+                    help="skip the GMRES time-to-1e-6 runs (mixed GMRES-IR vs FP64, plane-wave excitation)")
+    ap.add_argument("--solve-max-iter", type=int, default=1000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sched", type=int, default=0)
     ap.add_argument("--copy-probe", type=float, default=0.0,
@@ -284,16 +316,8 @@ def main():
     if not args.no_sched_study:
         result["schedule"] = sched_study(ctx, lay, x)
         log("schedule study: %s" % result["schedule"])
-    if args.solve:
-        b = torch.tensor(random_complex(n, 11), dtype=torch.complex128, device="cuda")
-        for name, prec in (("mixed", slim.SLIM_MIXED), ("fp64", slim.SLIM_FP64)):
-            xs = torch.zeros_like(b)
-            info, ok = ctx.solve(b, xs, tol=1e-6, restart=100, max_iter=args.solve_max_iter, prec=prec,
-                                 inner_tol=1e-2, scaled_rhs=True)
-            result["solve_" + name] = {"seconds": info.seconds, "iterations": info.iterations,
-                                       "outer": info.outer_steps, "rel_residual": info.rel_residual,
-                                       "converged": bool(ok)}
-            log("solve %s: %s" % (name, result["solve_" + name]))
+    if not args.no_solve:
+        result["solve"] = solve_study(ctx, lay, args.solve_max_iter)
     if not args.no_cpu_baseline:
         t0 = time.time()
         result["cpu_baseline"] = cpu_baseline(mesh, lay, freq, grid)

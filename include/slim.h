@@ -91,6 +91,22 @@ typedef struct {
   int64_t mem_budget;     /* bytes of device memory the build may use (0 = no cap)  */
   int32_t verbose;
   int32_t use_graphs;     /* slim_matvec replays one captured hipGraph per (prec, x, y) */
+  /* Conductor-block preconditioner of slim_solve (a reading of the constraint
+     preconditioner the paper uses in Sec. III-E, whose definition the paper does not give):
+     block Jacobi over conductors on the row-equilibrated system S A.  Each block
+     is S A restricted to one conductor's RWG edges and triangles, inverted in
+     FP64 and stored as complex64.  A conductor with more than precond_cap
+     unknowns is cut by recursive coordinate bisection of its triangle
+     centroids.  Each part is grown by precond_overlap rings of edge-adjacent
+     triangles and keeps its own rows of the extended block's inverse
+     (restricted additive Schwarz).  An edge belongs to the part of its T+.  */
+  int32_t precond;        /* 1 = build it (default), 0 = none                        */
+  int32_t precond_overlap;/* triangle rings added to a part of a cut conductor (2)     */
+  int64_t precond_cap;    /* max unknowns per block; 0 = choose the largest cap whose
+                             blocks fit precond_budget                                */
+  int64_t precond_budget; /* bytes for the stored blocks and their build buffers;
+                             0 = the free device memory after the rest of the build,
+                             less room for the solver's Krylov vectors               */
 } slim_build_opts;
 
 /* Fill `o` with the defaults used by the tests (near_cheb 3, n_far 4, n_near 5,
@@ -112,6 +128,9 @@ typedef struct {
   double mean_edge;                    /* h of the row scaling used by slim_solve */
   double build_seconds;
   int64_t device_bytes;                /* device memory held by the context      */
+  int64_t precond_blocks;              /* preconditioner blocks (0: none built)   */
+  int64_t precond_entries;             /* stored complex64 entries (rows x ext)   */
+  int64_t precond_cap;                 /* cap in effect (0: every conductor whole) */
 } slim_layout;
 
 typedef struct {
@@ -121,6 +140,8 @@ typedef struct {
   slim_prec prec;      /* FP64: plain GMRES; MIXED: GMRES-IR (FP64 outer residual) */
   double inner_tol;    /* MIXED: relative tolerance of each inner solve            */
   int32_t max_outer;
+  int32_t use_precond; /* 1: right-precondition with the conductor blocks (flexible
+                          GMRES, the preconditioned basis is kept) if they were built */
 } slim_solve_opts;
 
 typedef struct {
@@ -128,6 +149,7 @@ typedef struct {
   double rel_residual;        /* final true residual (FP64 operator)              */
   double seconds, matvec_seconds;
   int32_t n_matvec_fp64, n_matvec_mixed;
+  int32_t n_precond;          /* preconditioner applications                     */
 } slim_solve_info;
 
 /* --- context ----------------------------------------------------------- */
@@ -187,11 +209,34 @@ slim_status slim_rhs_planewave(slim_ctx* ctx, const double khat[3], const double
                                void* b_dev, void* stream);
 
 /* GMRES on S A x = S b with S = diag(1/h^2 (N_E rows), h (N_T rows)), h the
- * mean edge length (a change of length unit that balances the two row blocks).
+ * mean edge length (a change of length unit that balances the two row blocks),
+ * right-preconditioned by the conductor blocks when opts.use_precond = 1.
  * x_dev: in = x0, out = solution (complex128, n_sys).  b_dev is S b or b
  * according to `scaled_rhs` (1: b_dev already equilibrated).  Synchronous. */
 slim_status slim_solve(slim_ctx* ctx, const void* b_dev, int32_t scaled_rhs, void* x_dev,
                        const slim_solve_opts* opts, slim_solve_info* info, void* stream);
+
+/* z = P^{-1} v for the conductor-block preconditioner (built when
+ * opts.precond = 1): v, z are n_sys complex128 device vectors in the
+ * equilibrated space of slim_solve, no aliasing.  The blocks hold complex64
+ * entries; the product accumulates in FP32 and writes complex128.  Every unknown
+ * is written by exactly one block.  SLIM_E_STATE if no preconditioner was built. */
+slim_status slim_precond_apply(slim_ctx* ctx, const void* v_dev, void* z_dev, void* stream);
+/* Host copy of the preconditioner's blocks: *n_blocks, and the totals *n_ext
+ * (extended indices) and *n_own (owned rows).  ext_ptr (n_blocks+1 int64),
+ * ext_idx (n_ext int32 system indices: edges, then n_e + triangle, each
+ * ascending), own_ptr (n_blocks+1 int64) and own_pos (n_own int32 positions in
+ * the block's ext list).  Any array pointer may be NULL (sizes only). */
+slim_status slim_get_precond(const slim_ctx* ctx, int64_t* n_blocks, int64_t* n_ext, int64_t* n_own,
+                             int64_t* ext_ptr, int32_t* ext_idx, int64_t* own_ptr, int32_t* own_pos);
+
+/* Host-only (no device, no context): the blocks the preconditioner would use
+ * for a mesh, cap and overlap, in the slim_get_precond layout.  Same mesh
+ * rules and SLIM_E_MESH as slim_set_mesh.  Call with NULL arrays for the sizes. */
+slim_status slim_precond_partition(const double* xyz, int64_t n_vert, const int32_t* tri, int64_t n_tri,
+                                   const int32_t* obj_of_tri, int32_t n_obj, int64_t cap, int32_t overlap,
+                                   int64_t* n_blocks, int64_t* n_ext, int64_t* n_own, int64_t* ext_ptr,
+                                   int32_t* ext_idx, int64_t* own_ptr, int32_t* own_pos);
 
 /* Per-stage timing of slim_matvec with HIP events recorded on the caller's
  * stream around each kernel group: 0 internal blocks (A1, A2), 1 projection

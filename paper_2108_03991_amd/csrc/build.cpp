@@ -31,6 +31,8 @@ struct RocHandle {
       throw ::slim::Error(SLIM_E_HIP, std::string(#call) + " failed: " + std::to_string(int(st_))); \
   } while (0)
 
+}  // namespace
+
 // Candidate near triangle pairs (t <= u) in [t0, t1): centroid distance below
 // 1.01 c_near max(diam); the device takes the exact decision.
 std::vector<int32_t> near_candidates(const RWGTable& r, int64_t t0, int64_t t1, double c_near) {
@@ -158,8 +160,6 @@ void lu_solve(rocblas_handle h, int n, double* LU, const rocblas_int* ipiv, doub
     i1 = i0;
   }
 }
-
-}  // namespace
 
 Ctx::~Ctx() {
   drop_graphs();
@@ -392,6 +392,8 @@ void build_all(Ctx& c, const slim_build_opts& o) {
     pack_tiles(c, o.sched_mode == 1 ? 0 : o.sched_mode);
   }
   SLIM_HIP(hipStreamSynchronize(s));
+  build_precond(c, s);
+  if (o.precond) say("preconditioner done");
 
   slim_layout& Lo = c.layout;
   Lo = slim_layout{};
@@ -411,6 +413,9 @@ void build_all(Ctx& c, const slim_build_opts& o) {
   size_t freeb = 0, totalb = 0;
   (void)hipMemGetInfo(&freeb, &totalb);
   Lo.device_bytes = int64_t(totalb - freeb);
+  Lo.precond_blocks = c.pc_built ? int64_t(c.pc_blocks.size()) : 0;
+  Lo.precond_entries = c.pc_built ? c.pc_entries : 0;
+  Lo.precond_cap = c.pc_cap;
   c.built = true;
 }
 

@@ -53,6 +53,10 @@ void slim_default_build_opts(slim_build_opts* o) {
   o->internal_kernel = 0;
   o->slots = 0;
   o->use_graphs = 1;
+  o->precond = 1;
+  o->precond_overlap = 2;
+  o->precond_cap = 0;
+  o->precond_budget = 0;
 }
 
 slim_status slim_create(int32_t hip_device, slim_ctx** out) {
@@ -250,6 +254,71 @@ slim_status slim_solve(slim_ctx* h, const void* b, int32_t scaled_rhs, void* x, 
     if (st == SLIM_E_NOT_CONVERGED) h->c.last_error = "GMRES did not reach the tolerance";
     return st;
   });
+}
+
+slim_status slim_precond_apply(slim_ctx* h, const void* v, void* z, void* stream) {
+  return guard(h, [&]() {
+    SLIM_REQUIRE(h->c.built, SLIM_E_STATE, "operator not built");
+    SLIM_REQUIRE(h->c.pc_built, SLIM_E_STATE, "no preconditioner was built (build option precond = 0)");
+    SLIM_REQUIRE(v && z && v != z, SLIM_E_ARG, "null or aliased argument");
+    SLIM_HIP(hipSetDevice(h->c.device));
+    precond_apply(h->c, v, z, as_stream(stream));
+    return SLIM_OK;
+  });
+}
+
+slim_status slim_get_precond(const slim_ctx* hc, int64_t* n_blocks, int64_t* n_ext, int64_t* n_own, int64_t* ext_ptr,
+                             int32_t* ext_idx, int64_t* own_ptr, int32_t* own_pos) {
+  if (!hc) return SLIM_E_ARG;
+  slim_ctx* h = const_cast<slim_ctx*>(hc);
+  return guard(h, [&]() {
+    SLIM_REQUIRE(h->c.built, SLIM_E_STATE, "operator not built");
+    SLIM_REQUIRE(h->c.pc_built, SLIM_E_STATE, "no preconditioner was built (build option precond = 0)");
+    const Ctx& c = h->c;
+    if (n_blocks) *n_blocks = int64_t(c.pc_blocks.size());
+    if (n_ext) *n_ext = int64_t(c.pc_ext.size());
+    if (n_own) *n_own = int64_t(c.pc_own_pos.size());
+    if (ext_ptr) std::memcpy(ext_ptr, c.pc_ext_ptr.data(), c.pc_ext_ptr.size() * 8);
+    if (ext_idx && !c.pc_ext.empty()) std::memcpy(ext_idx, c.pc_ext.data(), c.pc_ext.size() * 4);
+    if (own_ptr) std::memcpy(own_ptr, c.pc_own_ptr.data(), c.pc_own_ptr.size() * 8);
+    if (own_pos && !c.pc_own_pos.empty()) std::memcpy(own_pos, c.pc_own_pos.data(), c.pc_own_pos.size() * 4);
+    return SLIM_OK;
+  });
+}
+
+slim_status slim_precond_partition(const double* xyz, int64_t n_vert, const int32_t* tri, int64_t n_tri,
+                                   const int32_t* obj, int32_t n_obj, int64_t cap, int32_t overlap, int64_t* n_blocks,
+                                   int64_t* n_ext, int64_t* n_own, int64_t* ext_ptr, int32_t* ext_idx, int64_t* own_ptr,
+                                   int32_t* own_pos) {
+  try {
+    if (!xyz || !tri || !obj || n_vert <= 0 || n_tri <= 0 || n_obj <= 0 || overlap < 0) return SLIM_E_ARG;
+    if (n_tri >= (int64_t(1) << 31) || n_vert >= (int64_t(1) << 31)) return SLIM_E_ARG;
+    Mesh m;
+    m.n_vert = n_vert;
+    m.n_tri = n_tri;
+    m.n_obj = n_obj;
+    m.xyz.assign(xyz, xyz + 3 * n_vert);
+    m.tri.assign(tri, tri + 3 * n_tri);
+    m.obj.assign(obj, obj + n_tri);
+    for (double v : m.xyz)
+      if (!std::isfinite(v)) return SLIM_E_MESH;
+    const RWGTable r = build_rwg(m);
+    std::vector<int64_t> ep, op;
+    std::vector<int32_t> ei, oi;
+    precond_partition(r, cap, overlap, ep, ei, op, oi);
+    if (n_blocks) *n_blocks = int64_t(ep.size()) - 1;
+    if (n_ext) *n_ext = int64_t(ei.size());
+    if (n_own) *n_own = int64_t(oi.size());
+    if (ext_ptr) std::memcpy(ext_ptr, ep.data(), ep.size() * 8);
+    if (ext_idx && !ei.empty()) std::memcpy(ext_idx, ei.data(), ei.size() * 4);
+    if (own_ptr) std::memcpy(own_ptr, op.data(), op.size() * 8);
+    if (own_pos && !oi.empty()) std::memcpy(own_pos, oi.data(), oi.size() * 4);
+    return SLIM_OK;
+  } catch (const Error& e) {
+    return e.code;
+  } catch (...) {
+    return SLIM_E_HIP;
+  }
 }
 
 slim_status slim_aim_convolve(slim_ctx* h, slim_prec prec, const void* src, void* dst, int32_t ncomp, void* stream) {

@@ -28,6 +28,17 @@ struct Block {
 
 template <class T> struct Cplx { T x, y; };
 
+// One stored block of the conductor-block preconditioner.
+struct PcBlk {
+  int64_t off;       // element offset of the n_own x ld complex64 rows
+  int64_t ext_off;   // first entry of the block in the gather list
+  int64_t row_off;   // first entry of the block in the owned-row list
+  int32_t n_ext;     // extended unknowns (columns)
+  int32_t ld;        // row length, n_ext rounded up to even
+  int32_t n_own;     // stored rows
+  int32_t pad;
+};
+
 struct Ctx {
   int device = 0;
   std::string last_error;
@@ -91,6 +102,16 @@ struct Ctx {
   DevBuf d_nP_ptr, d_nP_col, d_nP_v128, d_nP_v64;     // columns pre-scaled by A_u
   int64_t nnz_A = 0, nnz_P = 0;
 
+  // ---- conductor-block preconditioner ----
+  bool pc_built = false;
+  std::vector<PcBlk> pc_blocks;
+  std::vector<int32_t> pc_ext, pc_own_pos;    // gather list (system indices); owned positions in it
+  std::vector<int64_t> pc_ext_ptr, pc_own_ptr;
+  DevBuf d_pc, d_pc_ext, d_pc_row, d_pc_blk, d_pc_vin, d_pc_tiles, d_pc_slot_start;
+  int pc_slots = 0;
+  int64_t pc_entries = 0, pc_cap = 0;
+  double pc_seconds = 0.0;
+
   // ---- vectors ----
   DevBuf d_x64, d_y64;                  // complex64 copies of x / scratch
   DevBuf d_e, d_g, d_j, d_a, d_phi;     // sized for complex128
@@ -139,6 +160,11 @@ void fft_forward_3d_c128(Ctx& c, double* data_full, hipStream_t s);   // full (2
 void aim_convolve(Ctx& c, bool fp64, int ncomp, hipStream_t s);        // oct_in -> oct_out, ncomp components
 // sched.cpp
 void pack_tiles(Ctx& c, int mode);
+// precond.hip
+void build_precond(Ctx& c, hipStream_t s);
+void precond_apply(Ctx& c, const void* v, void* z, hipStream_t s);
+void precond_partition(const RWGTable& r, int64_t cap, int overlap, std::vector<int64_t>& ext_ptr,
+                       std::vector<int32_t>& ext_idx, std::vector<int64_t>& own_ptr, std::vector<int32_t>& own_pos);
 // solve.cpp
 slim_status solve_gmres(Ctx& c, const void* b, int scaled_rhs, void* x, const slim_solve_opts& o,
                         slim_solve_info& info, hipStream_t s);

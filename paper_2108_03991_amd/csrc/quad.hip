@@ -330,6 +330,10 @@ struct AsmArgs {
   double* Lvec;              // vector part only (plain L_A) (or null)
   double* Lphi;              // n_t x n_t, IS/(A A') (or null)
   int64_t ld_e, ld_t;
+  // optional row selections for Lvec / Lphi: local edge (triangle) -> output row,
+  // -1 = not kept; the outputs are then (kept rows) x (all local columns), ld = kept rows
+  const int32_t* erow;
+  const int32_t* trow;
   double skip_mag;           // skip far pairs with |e^{-jkR}| below this at the closest approach
 };
 
@@ -371,8 +375,15 @@ __device__ void scatter_pair(const AsmArgs& g, int t, int u, Cx IA[9], Cx IS, Cx
       }
       if (g.Lvec) {
         Cx v = {cv * a.r, cv * a.i};
-        atomic_c(g.Lvec, ml + nl * g.ld_e, v);
-        if (t != u) atomic_c(g.Lvec, nl + ml * g.ld_e, v);
+        if (!g.erow) {
+          atomic_c(g.Lvec, ml + nl * g.ld_e, v);
+          if (t != u) atomic_c(g.Lvec, nl + ml * g.ld_e, v);
+        } else {
+          // symmetric matrix: entry (m, n) and its mirror (n, m), each kept if its row is selected
+          const int rm = g.erow[ml], rn = g.erow[nl];
+          if (rm >= 0) atomic_c(g.Lvec, rm + nl * g.ld_e, v);
+          if (t != u && rn >= 0) atomic_c(g.Lvec, rn + ml * g.ld_e, v);
+        }
       }
       if (WANT_K && g.Kk) {
         Cx v = {cv * IK[3 * i + j].r, cv * IK[3 * i + j].i};
@@ -384,8 +395,14 @@ __device__ void scatter_pair(const AsmArgs& g, int t, int u, Cx IA[9], Cx IS, Cx
   if (g.Lphi) {
     Cx v = {IS.r / (At * Au), IS.i / (At * Au)};
     int64_t tl = t - g.t0, ul = u - g.t0;
-    atomic_c(g.Lphi, tl + ul * g.ld_t, v);
-    if (t != u) atomic_c(g.Lphi, ul + tl * g.ld_t, v);
+    if (!g.trow) {
+      atomic_c(g.Lphi, tl + ul * g.ld_t, v);
+      if (t != u) atomic_c(g.Lphi, ul + tl * g.ld_t, v);
+    } else {
+      const int rt = g.trow[tl], ru = g.trow[ul];
+      if (rt >= 0) atomic_c(g.Lphi, rt + ul * g.ld_t, v);
+      if (t != u && ru >= 0) atomic_c(g.Lphi, ru + tl * g.ld_t, v);
+    }
   }
 }
 
@@ -443,6 +460,7 @@ void launch_assemble(const AsmLaunch& L, hipStream_t s) {
   g.inv_k2r = ik2.real(); g.inv_k2i = ik2.imag();
   g.Lk = L.Lk; g.Kk = L.Kk; g.Lvec = L.Lvec; g.Lphi = L.Lphi;
   g.ld_e = L.ld_e; g.ld_t = L.ld_t;
+  g.erow = L.erow; g.trow = L.trow;
   g.skip_mag = L.skip_mag;
   const int n = L.t1 - L.t0;
   dim3 grid((n + 15) / 16, (n + 15) / 16);

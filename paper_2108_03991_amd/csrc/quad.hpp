@@ -30,6 +30,8 @@ struct AsmLaunch {
   double* Lvec = nullptr;
   double* Lphi = nullptr;
   int64_t ld_e = 0, ld_t = 0;
+  const int32_t* erow = nullptr;          // row selections of Lvec / Lphi (local index -> row, -1 skip)
+  const int32_t* trow = nullptr;
   const int32_t* near_pairs = nullptr;   // candidate (t, u) pairs, t <= u
   int64_t n_near_pairs = 0;
   double skip_mag = 0.0;

@@ -4,11 +4,14 @@
 // The system is solved in the row-equilibrated form S A x = S b with
 // S = diag(1/h^2 on the tested-EFIE rows, h on the continuity rows), h the mean
 // edge length: this is the change of length unit to h, which balances the two
-// row blocks (in SI units they differ by about h^3).  No other preconditioner.
-//   FP64: restarted GMRES(m), classical Gram-Schmidt applied twice (CGS2),
+// row blocks (in SI units they differ by about h^3).  Optionally right-
+// preconditioned by the conductor blocks (precond.hip).  Those are applied in
+// complex64, so the cycle is flexible GMRES [Saad1993]: the preconditioned
+// vectors z_k = P^{-1} v_k are kept and the update is d = sum_k y_k z_k.
+//   FP64: restarted (F)GMRES(m), classical Gram-Schmidt applied twice (CGS2),
 //         Givens rotations, FP64 true residual at every restart.
 //   MIXED: GMRES-IR -- outer residual r = S (b - A x) with the FP64 operator;
-//         inner GMRES(m) with the mixed-precision operator on S A d = r
+//         inner (F)GMRES(m) with the mixed-precision operator on S A d = r
 //         (FP64 Krylov basis and orthogonalisation); x += d.
 #include <chrono>
 #include <cstdio>
@@ -122,14 +125,17 @@ struct Krylov {
   hipStream_t s;
   int64_t n, ne;
   double s1, s2;
-  DevBuf V, w, partial, hdev, y, r, tmp;
+  DevBuf V, Zb, w, partial, hdev, y, r, tmp;
   int m;
-  Krylov(Ctx& c_, hipStream_t s_, int m_) : c(c_), s(s_), m(m_) {
+  bool pc;
+  int n_precond = 0;
+  Krylov(Ctx& c_, hipStream_t s_, int m_, bool pc_) : c(c_), s(s_), m(m_), pc(pc_) {
     ne = c.rwg.n_e;
     n = c.rwg.n_e + c.rwg.n_t;
     s1 = 1.0 / (c.rwg.mean_edge * c.rwg.mean_edge);
     s2 = c.rwg.mean_edge;
     V.alloc(size_t(m + 1) * n * 16);
+    if (pc) Zb.alloc(size_t(m) * n * 16);
     w.alloc(size_t(n) * 16);
     r.alloc(size_t(n) * 16);
     y.alloc(size_t(n) * 16);
@@ -138,6 +144,7 @@ struct Krylov {
     hdev.alloc(size_t(m + 2) * 16);
   }
   double2* Vi(int i) { return V.as<double2>() + int64_t(i) * n; }
+  double2* Zi(int i) { return Zb.as<double2>() + int64_t(i) * n; }
   void dots(int nv, const double2* vec, std::vector<cd>& out) {
     hipLaunchKernelGGL(k_multidot, dim3(kDotBlocks), dim3(256), 0, s, V.as<double2>(), n, nv, vec, n,
                        partial.as<double2>());
@@ -176,7 +183,13 @@ struct Krylov {
     int k = 0;
     est = beta;
     for (; k < std::min(m, max_it); ++k) {
-      op(p, Vi(k), w.as<double2>());
+      if (pc) {
+        precond_apply(c, Vi(k), Zi(k), s);
+        n_precond++;
+        op(p, Zi(k), w.as<double2>());
+      } else {
+        op(p, Vi(k), w.as<double2>());
+      }
       for (int pass = 0; pass < 2; ++pass) {   // CGS2
         dots(k + 1, w.as<double2>(), h);
         SLIM_HIP(hipMemcpyAsync(hdev.p, h.data(), size_t(k + 1) * 16, hipMemcpyHostToDevice, s));
@@ -214,7 +227,8 @@ struct Krylov {
       yv[i] = acc / Hm[size_t(i) * m + i];
     }
     SLIM_HIP(hipMemcpyAsync(hdev.p, yv.data(), size_t(k) * 16, hipMemcpyHostToDevice, s));
-    hipLaunchKernelGGL(k_update, dim3(nblk(n)), dim3(256), 0, s, V.as<double2>(), n, k, hdev.as<double2>(), d, n);
+    hipLaunchKernelGGL(k_update, dim3(nblk(n)), dim3(256), 0, s, pc ? Zb.as<double2>() : V.as<double2>(), n, k,
+                       hdev.as<double2>(), d, n);
     SLIM_HIP(hipGetLastError());
     SLIM_HIP(hipStreamSynchronize(s));
     return k;
@@ -229,7 +243,9 @@ slim_status solve_gmres(Ctx& c, const void* b, int scaled_rhs, void* x, const sl
   const int m = o.restart > 0 ? o.restart : 50;
   const double tol = o.tol > 0 ? o.tol : 1e-6;
   const int max_iter = o.max_iter > 0 ? o.max_iter : 1000;
-  Krylov K(c, s, m);
+  SLIM_REQUIRE(!o.use_precond || c.pc_built, SLIM_E_STATE,
+               "use_precond = 1 but no preconditioner was built (build option precond = 0)");
+  Krylov K(c, s, m, o.use_precond != 0);
   const double2* B = reinterpret_cast<const double2*>(b);
   double2* X = reinterpret_cast<double2*>(x);
   // ||S b||  (residual of y = 0)
@@ -276,6 +292,7 @@ slim_status solve_gmres(Ctx& c, const void* b, int scaled_rhs, void* x, const sl
   }
   SLIM_HIP(hipStreamSynchronize(s));
   info.iterations = its;
+  info.n_precond = K.n_precond;
   info.outer_steps = outer;
   info.rel_residual = rel;
   info.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();

@@ -31,7 +31,9 @@ class BuildOpts(C.Structure):
                 ("n_far", C.c_int32), ("n_near", C.c_int32), ("levels", C.c_int32), ("n_r", C.c_int32),
                 ("n_t", C.c_int32), ("q", C.c_double), ("c_near", C.c_double), ("sched_mode", C.c_int32),
                 ("tile_rows", C.c_int32), ("internal_kernel", C.c_int32), ("slots", C.c_int32),
-                ("mem_budget", C.c_int64), ("verbose", C.c_int32), ("use_graphs", C.c_int32)]
+                ("mem_budget", C.c_int64), ("verbose", C.c_int32), ("use_graphs", C.c_int32),
+                ("precond", C.c_int32), ("precond_overlap", C.c_int32), ("precond_cap", C.c_int64),
+                ("precond_budget", C.c_int64)]
 
 
 class Layout(C.Structure):
@@ -39,18 +41,19 @@ class Layout(C.Structure):
                 ("grid", C.c_int32 * 3), ("grid_h", C.c_double * 3), ("grid_origin", C.c_double * 3),
                 ("nnz_near_A", C.c_int64), ("nnz_near_phi", C.c_int64), ("internal_entries", C.c_int64),
                 ("n_tiles", C.c_int64), ("slots", C.c_int32), ("tile_rows", C.c_int32), ("mean_edge", C.c_double),
-                ("build_seconds", C.c_double), ("device_bytes", C.c_int64)]
+                ("build_seconds", C.c_double), ("device_bytes", C.c_int64), ("precond_blocks", C.c_int64),
+                ("precond_entries", C.c_int64), ("precond_cap", C.c_int64)]
 
 
 class SolveOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("restart", C.c_int32), ("max_iter", C.c_int32), ("prec", C.c_int32),
-                ("inner_tol", C.c_double), ("max_outer", C.c_int32)]
+                ("inner_tol", C.c_double), ("max_outer", C.c_int32), ("use_precond", C.c_int32)]
 
 
 class SolveInfo(C.Structure):
     _fields_ = [("iterations", C.c_int32), ("outer_steps", C.c_int32), ("rel_residual", C.c_double),
                 ("seconds", C.c_double), ("matvec_seconds", C.c_double), ("n_matvec_fp64", C.c_int32),
-                ("n_matvec_mixed", C.c_int32)]
+                ("n_matvec_mixed", C.c_int32), ("n_precond", C.c_int32)]
 
 
 class Material(C.Structure):
@@ -100,13 +103,17 @@ def lib():
         L.slim_aim_convolve.argtypes = [vp, i32, vp, vp, i32, vp]
         L.slim_get_aim.argtypes = [vp, vp, vp, vp, vp]
         L.slim_get_near.argtypes = [vp, i32, vp, vp, vp]
+        L.slim_precond_apply.argtypes = [vp, vp, vp, vp]
+        L.slim_get_precond.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
+        L.slim_precond_partition.argtypes = [vp, i64, vp, i64, vp, i32, i64, i32, vp, vp, vp, vp, vp, vp, vp]
         L.slim_profile.argtypes = [vp, i32]
         L.slim_profile_read.argtypes = [vp, dp, C.POINTER(i64)]
         for name in ("slim_create", "slim_set_mesh", "slim_set_materials", "slim_build", "slim_get_layout",
                      "slim_get_rwg", "slim_matvec", "slim_matvec_parts", "slim_internal_apply",
                      "slim_rhs_planewave", "slim_solve", "slim_sched_record", "slim_sched_tiles",
                      "slim_sched_train", "slim_sched_set_mode", "slim_mlp_forward_backward", "slim_profile",
-                     "slim_profile_read", "slim_aim_convolve", "slim_get_aim", "slim_get_near"):
+                     "slim_profile_read", "slim_aim_convolve", "slim_get_aim", "slim_get_near",
+                     "slim_precond_apply", "slim_get_precond", "slim_precond_partition"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -116,7 +123,8 @@ EXPORTS = ["slim_default_build_opts", "slim_create", "slim_destroy", "slim_last_
            "slim_set_materials", "slim_build", "slim_get_layout", "slim_get_rwg", "slim_matvec",
            "slim_matvec_parts", "slim_internal_apply", "slim_rhs_planewave", "slim_solve", "slim_sched_record",
            "slim_sched_tiles", "slim_sched_train", "slim_sched_set_mode", "slim_mlp_forward_backward",
-           "slim_profile", "slim_profile_read", "slim_aim_convolve", "slim_get_aim", "slim_get_near"]
+           "slim_profile", "slim_profile_read", "slim_aim_convolve", "slim_get_aim", "slim_get_near",
+           "slim_precond_apply", "slim_get_precond", "slim_precond_partition"]
 
 
 def _ptr(t):
@@ -216,14 +224,29 @@ class Context:
         self._check(lib().slim_rhs_planewave(self._h, k, e, _ptr(b), _stream(stream)))
 
     def solve(self, b, x, tol=1e-6, restart=50, max_iter=1000, prec=SLIM_FP64, inner_tol=1e-4, max_outer=0,
-              scaled_rhs=False, stream=None):
-        o = SolveOpts(tol, restart, max_iter, prec, inner_tol, max_outer)
+              scaled_rhs=False, use_precond=True, stream=None):
+        o = SolveOpts(tol, restart, max_iter, prec, inner_tol, max_outer, int(bool(use_precond)))
         info = SolveInfo()
         st = lib().slim_solve(self._h, _ptr(b), int(bool(scaled_rhs)), _ptr(x), C.byref(o), C.byref(info),
                               _stream(stream))
         if st not in (0, 7):
             self._check(st)
         return info, st == 0
+
+    def precond_apply(self, v, z, stream=None):
+        self._check(lib().slim_precond_apply(self._h, _ptr(v), _ptr(z), _stream(stream)))
+
+    def get_precond(self):
+        """Blocks of the preconditioner: list of (ext system indices, owned positions)."""
+        nb, ne_, no = C.c_int64(0), C.c_int64(0), C.c_int64(0)
+        self._check(lib().slim_get_precond(self._h, C.byref(nb), C.byref(ne_), C.byref(no), None, None, None, None))
+        ep = np.zeros(nb.value + 1, np.int64)
+        ei = np.zeros(max(1, ne_.value), np.int32)
+        op = np.zeros(nb.value + 1, np.int64)
+        oi = np.zeros(max(1, no.value), np.int32)
+        self._check(lib().slim_get_precond(self._h, C.byref(nb), C.byref(ne_), C.byref(no), ep.ctypes.data,
+                                           ei.ctypes.data, op.ctypes.data, oi.ctypes.data))
+        return [(ei[ep[k]:ep[k + 1]].copy(), oi[op[k]:op[k + 1]].copy()) for k in range(nb.value)]
 
     def aim_convolve(self, prec, src, dst, ncomp, stream=None):
         self._check(lib().slim_aim_convolve(self._h, prec, _ptr(src), _ptr(dst), int(ncomp), _stream(stream)))
@@ -269,6 +292,27 @@ class Context:
 
     def sched_set_mode(self, mode):
         self._check(lib().slim_sched_set_mode(self._h, int(mode)))
+
+
+def precond_partition(verts, tris, obj, n_obj, cap, overlap):
+    """Host-only block partition of the preconditioner: list of (ext indices, owned positions)."""
+    v = np.ascontiguousarray(verts, dtype=np.float64)
+    t = np.ascontiguousarray(tris, dtype=np.int32)
+    o = np.ascontiguousarray(obj, dtype=np.int32)
+    nb, ne_, no = C.c_int64(0), C.c_int64(0), C.c_int64(0)
+    args = (v.ctypes.data, v.shape[0], t.ctypes.data, t.shape[0], o.ctypes.data, int(n_obj), int(cap), int(overlap))
+    st = lib().slim_precond_partition(*args, C.byref(nb), C.byref(ne_), C.byref(no), None, None, None, None)
+    if st != 0:
+        raise SlimError(st, "slim_precond_partition failed")
+    ep = np.zeros(nb.value + 1, np.int64)
+    ei = np.zeros(max(1, ne_.value), np.int32)
+    op = np.zeros(nb.value + 1, np.int64)
+    oi = np.zeros(max(1, no.value), np.int32)
+    st = lib().slim_precond_partition(*args, C.byref(nb), C.byref(ne_), C.byref(no), ep.ctypes.data, ei.ctypes.data,
+                                      op.ctypes.data, oi.ctypes.data)
+    if st != 0:
+        raise SlimError(st, "slim_precond_partition failed")
+    return [(ei[ep[k]:ep[k + 1]].copy(), oi[op[k]:op[k + 1]].copy()) for k in range(nb.value)]
 
 
 def mlp_forward_backward(F, B, params, X, t, y, grad, loss, stream=None):

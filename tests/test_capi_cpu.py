@@ -2,6 +2,8 @@
 import ctypes
 import re
 
+import numpy as np
+
 import pytest
 
 
@@ -44,3 +46,23 @@ def test_single_hip_runtime_in_process():
     hip = {line.split()[-1] for line in maps if 'libamdhip64' in line}
     hsa = {line.split()[-1] for line in maps if 'libhsa-runtime64' in line}
     assert len(hip) == 1 and len(hsa) == 1, (hip, hsa)
+
+
+@pytest.mark.parametrize("cap,overlap", [(0, 2), (120, 0), (120, 2), (60, 3), (300, 1)])
+def test_precond_partition_matches_oracle(cap, overlap):
+    """Host logic of the preconditioner: the library's block partition (RCB, growth,
+    T+ ownership) equals the oracle's, index for index."""
+    from inputs.geometry import box_mesh, merge, small_boxes
+    from oracle import precond as opc
+    from oracle.rwg import build_rwg
+    from paper_2108_03991_amd import slim
+    for m in (merge([box_mesh((0.0, 0.0, 0.0), (20e-6, 2e-6, 2e-6), (20, 2, 2)),
+                     box_mesh((25e-6, 0.0, 0.0), (4e-6, 2e-6, 2e-6), (4, 2, 2)),
+                     box_mesh((32e-6, 0.0, 0.0), (3e-6, 1e-6, 1e-6), (3, 1, 1))]),
+              small_boxes(4, seed=5, tri_range=(40, 200))):
+        g = build_rwg(m.verts, m.tris, m.obj, m.n_obj)
+        ref = opc.partition(g, cap=cap, overlap=overlap)
+        got = slim.precond_partition(m.verts, m.tris, m.obj, m.n_obj, cap, overlap)
+        assert len(got) == len(ref)
+        for (ext, pos), b in zip(got, ref):
+            assert np.array_equal(ext, b.ext) and np.array_equal(pos, b.own_pos)

@@ -9,8 +9,9 @@ from tests.gpu_util import context
 pytestmark = pytest.mark.gpu
 
 
+@pytest.mark.parametrize("use_precond", [False, True])
 @pytest.mark.parametrize("prec", [0, 1])
-def test_gmres_matches_lu(c1_mesh, c1_system, prec):
+def test_gmres_matches_lu(c1_mesh, c1_system, prec, use_precond):
     import torch
     ctx, lay = context(c1_mesh, freq=10e9, grid=(0, 0, 0))
     S = c1_system
@@ -22,14 +23,17 @@ def test_gmres_matches_lu(c1_mesh, c1_system, prec):
     b = torch.tensor(r, device='cuda')
     x = torch.zeros_like(b)
     info, ok = ctx.solve(b, x, tol=1e-8, restart=300, max_iter=6000, prec=prec, inner_tol=1e-3,
-                         scaled_rhs=True)
+                         scaled_rhs=True, use_precond=use_precond)
     assert ok and info.rel_residual <= 1e-8
     xg = x.cpu().numpy()
     cond = np.linalg.cond(A)
     assert np.linalg.norm(A @ xg - r) <= 1.01e-8 * np.linalg.norm(r) * 10
     assert np.linalg.norm(xg - xs) / np.linalg.norm(xs) <= 10 * cond * 1e-8
-    if prec == 1:
+    if prec == 1 and not use_precond:
         assert info.n_matvec_mixed > info.n_matvec_fp64
+    if use_precond:
+        # one conductor: the block is the whole equilibrated system
+        assert info.iterations <= 10 and info.n_precond == info.iterations
 
 
 def test_gmres_not_converged_returns_best_iterate(c1_mesh):
@@ -37,5 +41,5 @@ def test_gmres_not_converged_returns_best_iterate(c1_mesh):
     ctx, lay = context(c1_mesh, freq=10e9, grid=(0, 0, 0))
     b = torch.tensor(random_complex(lay.n_sys, 1), device='cuda')
     x = torch.zeros_like(b)
-    info, ok = ctx.solve(b, x, tol=1e-12, restart=20, max_iter=40, prec=0, scaled_rhs=True)
+    info, ok = ctx.solve(b, x, tol=1e-12, restart=20, max_iter=40, prec=0, scaled_rhs=True, use_precond=False)
     assert not ok and info.iterations == 40 and 0 < info.rel_residual < 1
