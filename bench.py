@@ -173,13 +173,13 @@ def solve_study(ctx, lay, max_iter):
     n = lay.n_sys
     b = torch.zeros(n, dtype=torch.complex128, device="cuda")
     ctx.rhs_planewave((0.0, 0.0, -1.0), (1.0, 0.0, 0.0), b)
-    out = {"rhs": "plane wave, E0 = 1 V/m along x, travelling along -z", "tol": 1e-6, "restart": 50,
+    out = {"rhs": "plane wave, E0 = 1 V/m along x, travelling along -z", "tol": 1e-6, "restart": 100,
            "precond": {"blocks": lay.precond_blocks, "entries": lay.precond_entries, "cap": lay.precond_cap}}
     sols = {}
     for name, prec in (("mixed", slim.SLIM_MIXED), ("fp64", slim.SLIM_FP64)):
         xs = torch.zeros_like(b)
         torch.cuda.synchronize()
-        info, ok = ctx.solve(b, xs, tol=1e-6, restart=50, max_iter=max_iter, prec=prec, inner_tol=1e-2)
+        info, ok = ctx.solve(b, xs, tol=1e-6, restart=100, max_iter=max_iter, prec=prec, inner_tol=1e-2)
         out[name] = {"seconds": info.seconds, "iterations": info.iterations, "outer": info.outer_steps,
                      "precond_applies": info.n_precond, "matvecs_mixed": info.n_matvec_mixed,
                      "matvecs_fp64": info.n_matvec_fp64, "rel_residual": info.rel_residual, "converged": bool(ok)}

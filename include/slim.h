@@ -97,9 +97,11 @@ typedef struct {
      is S A restricted to one conductor's RWG edges and triangles, inverted in
      FP64 and stored as complex64.  A conductor with more than precond_cap
      unknowns is cut by recursive coordinate bisection of its triangle
-     centroids.  Each part is grown by precond_overlap rings of edge-adjacent
-     triangles and keeps its own rows of the extended block's inverse
-     (restricted additive Schwarz).  An edge belongs to the part of its T+.  */
+     centroids.  Each part is grown by max(precond_overlap, 1) rings of
+     edge-adjacent triangles; its extended block holds those triangles and the
+     edges with both triangles among them (no current crosses a cut), and it
+     keeps its own rows of that block's inverse (restricted additive Schwarz).
+     An edge belongs to the part of its T+.  */
   int32_t precond;        /* 1 = build it (default), 0 = none                        */
   int32_t precond_overlap;/* triangle rings added to a part of a cut conductor (2)     */
   int64_t precond_cap;    /* max unknowns per block; 0 = choose the largest cap whose

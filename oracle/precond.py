@@ -18,10 +18,15 @@ coordinate bisection (RCB) of its triangle centroids. The rules:
   - stop once a part has at most `cap` unknowns, an unknown being an owned edge
     or a triangle.
 An edge belongs to the part that holds its T+ triangle. A part is grown by
-`overlap` rings of edge-adjacent triangles of the same conductor. The extended
-index set is its grown triangles plus the edges whose T+ lies among them. The
-part's rows of the inverse of the extended block are kept (restricted additive
-Schwarz).
+max(overlap, 1) rings of edge-adjacent triangles of the same conductor.
+The extended block holds the grown triangles and the edges with both
+triangles among them. So no current crosses the boundary of the extended
+set: each part is solved as an isolated piece of conductor. If edges with
+only their T+ inside were kept, they would carry current through the cut
+with no charge to balance it. At low frequency those currents are governed
+by the tiny j k0 L_A term alone, and the local inverse then amplifies them
+without bound. The part's rows of the inverse of the extended block are
+kept (restricted additive Schwarz).
 """
 from __future__ import annotations
 
@@ -74,6 +79,11 @@ def grow(g: RWG, tris: np.ndarray, layers: int) -> np.ndarray:
     return np.array(sorted(cur), dtype=np.int64)
 
 
+def _edges_inside(g: RWG, tri_set: np.ndarray) -> np.ndarray:
+    """Edges with both triangles in the given set (ascending)."""
+    return np.nonzero(np.isin(g.tplus, tri_set) & np.isin(g.tminus, tri_set))[0]
+
+
 def partition(g: RWG, cap: int = 0, overlap: int = 2) -> list:
     """Blocks of the preconditioner; cap <= 0 keeps every conductor whole."""
     blocks = []
@@ -81,8 +91,8 @@ def partition(g: RWG, cap: int = 0, overlap: int = 2) -> list:
         tris = np.arange(g.obj_tri_off[i], g.obj_tri_off[i + 1])
         parts = [tris] if cap <= 0 else rcb_parts(g, tris, cap)
         for p in parts:
-            ext_t = p if len(parts) == 1 else grow(g, p, overlap)
-            ext_e = _edges_with_tplus_in(g, ext_t)
+            ext_t = p if len(parts) == 1 else grow(g, p, max(overlap, 1))
+            ext_e = _edges_inside(g, ext_t)
             own_e = _edges_with_tplus_in(g, p)
             ext = np.concatenate([ext_e, g.n_e + ext_t])
             own_pos = np.concatenate([np.searchsorted(ext_e, own_e),

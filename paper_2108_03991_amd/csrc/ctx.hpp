@@ -111,6 +111,7 @@ struct Ctx {
   int pc_slots = 0;
   int64_t pc_entries = 0, pc_cap = 0;
   double pc_seconds = 0.0;
+  std::vector<double> pc_cond;                // 1-norm condition number of every block (FP64 inverse)
 
   // ---- vectors ----
   DevBuf d_x64, d_y64;                  // complex64 copies of x / scratch

@@ -19,10 +19,14 @@
 //  - stable order by that coordinate, the first half takes size/2 triangles;
 //  - stop at <= cap unknowns, counting owned edges plus triangles;
 //  - an edge belongs to the part that holds its T+.
-// Each part is grown by `overlap` rings of edge-adjacent triangles. The
-// extended set holds those triangles and the edges whose T+ lies among them.
-// A part keeps its own rows of the extended block's inverse (restricted
-// additive Schwarz). Every unknown is written by exactly one block.
+// Each part is grown by max(overlap, 1) rings of edge-adjacent triangles. The
+// extended set holds those triangles and the edges with both triangles among
+// them. No current crosses the boundary of a part, so it is solved as an
+// isolated piece of conductor. An edge cut open instead would carry current
+// whose charge lies outside the block, governed only by j k0 L_A; at low
+// frequency its local inverse blows up. A part keeps its own rows of the
+// extended block's inverse (restricted additive Schwarz). Every unknown is
+// written by exactly one block.
 //
 // Storing the rows in complex64 makes the preconditioner only approximately
 // linear, so the solver uses flexible GMRES.
@@ -128,6 +132,19 @@ struct Partitioner {
     std::sort(e.begin(), e.end());
     return e;
   }
+  // edges with both triangles in the set: no current crosses the block boundary
+  std::vector<int32_t> edges_inside(const std::vector<int32_t>& tris) {
+    for (int32_t t : tris) mark[size_t(t)] = 1;
+    std::vector<int32_t> e;
+    for (int32_t t : tris)
+      for (int k = 0; k < 3; ++k) {
+        const int32_t ed = r.tri_edge[3 * size_t(t) + k];
+        if (r.tplus[size_t(ed)] == t && mark[size_t(r.tminus[size_t(ed)])]) e.push_back(ed);
+      }
+    for (int32_t t : tris) mark[size_t(t)] = 0;
+    std::sort(e.begin(), e.end());
+    return e;
+  }
   std::vector<Part> partition(int64_t cap, int overlap) {
     std::vector<Part> parts;
     for (int32_t i = 0; i < r.n_obj; ++i) {
@@ -139,8 +156,8 @@ struct Partitioner {
       for (auto& p : pl) {
         Part q;
         q.obj = i;
-        q.ext_t = pl.size() == 1 ? p : grow(p, overlap);
-        q.ext_e = edges_with_tplus_in(q.ext_t);
+        q.ext_t = pl.size() == 1 ? p : grow(p, std::max(overlap, 1));
+        q.ext_e = edges_inside(q.ext_t);
         const std::vector<int32_t> own_e = edges_with_tplus_in(p);
         for (int32_t e : own_e)
           q.own_pos.push_back(int32_t(std::lower_bound(q.ext_e.begin(), q.ext_e.end(), e) - q.ext_e.begin()));
@@ -274,6 +291,86 @@ __global__ void k_pc_fill(FillArgs a) {
     v = make_double2(0.0, a.k0 * a.s2);   // h j k0
   }
   a.B[i] = v;
+}
+
+// max over columns of the column sums of |B| (s x s, column-major): one workgroup per column
+__global__ void k_pc_colsum(const double2* B, int64_t s, double* out) {
+  const int64_t c = blockIdx.x;
+  double acc = 0.0;
+  for (int64_t r = threadIdx.x; r < s; r += blockDim.x) {
+    const double2 v = B[r + c * s];
+    acc += sqrt(v.x * v.x + v.y * v.y);
+  }
+  __shared__ double red[256];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (int(threadIdx.x) < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[c] = red[0];
+}
+
+// Green's function over a box of integer grid offsets [lo, lo + D) per axis (G(0) = 0)
+__global__ void k_pc_gtab(double2* T, int lx, int ly, int lz, int Dx, int Dy, int Dz, double hx, double hy, double hz,
+                          double k0) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= int64_t(Dx) * Dy * Dz) return;
+  const int x = int(i % Dx) + lx, y = int((i / Dx) % Dy) + ly, z = int(i / (int64_t(Dx) * Dy)) + lz;
+  const double dx = x * hx, dy = y * hy, dz = z * hz;
+  const double R = sqrt(dx * dx + dy * dy + dz * dz);
+  double2 v = make_double2(0.0, 0.0);
+  if (R > 0.0) {
+    double sn, cs;
+    sincos(k0 * R, &sn, &cs);
+    v = make_double2(cs / (4.0 * 3.14159265358979323846 * R), -sn / (4.0 * 3.14159265358979323846 * R));
+  }
+  T[i] = v;
+}
+
+// The AIM operator applies L exactly only on near pairs (stencil centres within
+// Chebyshev distance near_cheb) and through the grid elsewhere: replace every
+// far entry of the assembled exact rows by its grid value
+//   sum_c sum_a sum_b w_c[m, a] G(node_a(m) - node_b(n)) w_c[n, b],
+// so that the block is the self part of the operator that is being solved.
+struct FarArgs {
+  double2* L; int64_t ld; int64_t rows, cols;   // column-major rows x cols
+  const int32_t* row_local;                     // row -> local basis index
+  int base;                                     // global index of local basis 0
+  const int32_t* cidx; const double* w; int ncomp, near_cheb;
+  const double2* gtab; int lx, ly, lz, Dx, Dy;
+};
+
+__global__ void k_pc_far_grid(FarArgs a) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= a.rows * a.cols) return;
+  const int64_t r = i % a.rows, col = i / a.rows;
+  const int m = a.base + a.row_local[r], n = a.base + int(col);
+  const int dx = a.cidx[3 * m] - a.cidx[3 * n], dy = a.cidx[3 * m + 1] - a.cidx[3 * n + 1],
+            dz = a.cidx[3 * m + 2] - a.cidx[3 * n + 2];
+  if (max(abs(dx), max(abs(dy), abs(dz))) <= a.near_cheb) return;
+  const double* wm = a.w + int64_t(m) * 27 * a.ncomp;
+  const double* wn = a.w + int64_t(n) * 27 * a.ncomp;
+  double sr = 0.0, si = 0.0;
+  for (int p = 0; p < 27; ++p) {
+    const int px = p % 3 - 1, py = (p / 3) % 3 - 1, pz = p / 9 - 1;
+    double tr[3] = {0, 0, 0}, ti[3] = {0, 0, 0};
+    for (int q = 0; q < 27; ++q) {
+      const int qx = q % 3 - 1, qy = (q / 3) % 3 - 1, qz = q / 9 - 1;
+      const int ox = dx + px - qx - a.lx, oy = dy + py - qy - a.ly, oz = dz + pz - qz - a.lz;
+      const double2 G = a.gtab[(int64_t(oz) * a.Dy + oy) * a.Dx + ox];
+      for (int c = 0; c < a.ncomp; ++c) {
+        const double wv = wn[c * 27 + q];
+        tr[c] += G.x * wv;
+        ti[c] += G.y * wv;
+      }
+    }
+    for (int c = 0; c < a.ncomp; ++c) {
+      sr += wm[c * 27 + p] * tr[c];
+      si += wm[c * 27 + p] * ti[c];
+    }
+  }
+  a.L[r + col * a.ld] = make_double2(sr, si);
 }
 
 __global__ void k_pc_eye(double2* X, int64_t s) {
@@ -496,7 +593,9 @@ void build_precond(Ctx& c, hipStream_t s) {
   c.d_pc_row.upload(rowidx);
   c.d_pc_blk.upload(c.pc_blocks);
   c.d_pc_vin.alloc(std::max<size_t>(1, c.pc_ext.size()) * 8);
-  DevBuf la, lp, mc, w, B, X, ipiv, emap, tmap, dE, dT, dpos, dpairs, info;
+  DevBuf la, lp, mc, w, B, X, ipiv, emap, tmap, dE, dT, dpos, dpairs, info, colsum;
+  colsum.alloc(std::max<size_t>(8, plan.t_ipiv * 2 + 8));
+  c.pc_cond.clear();
   la.alloc(std::max<size_t>(16, plan.t_la));
   lp.alloc(std::max<size_t>(16, plan.t_lp));
   mc.alloc(std::max<size_t>(16, plan.t_mc));
@@ -520,6 +619,14 @@ void build_precond(Ctx& c, hipStream_t s) {
   const double hmean = r.mean_edge;
   int32_t pairs_obj = -1;
   std::vector<int32_t> pairs;
+  // AIM consistency: stencil centres on the device and a per-conductor Green's function table
+  DevBuf d_cidx_e, d_cidx_t, gtab, dR;
+  int32_t gtab_obj = -1;
+  int gl[3] = {0, 0, 0}, gD[3] = {1, 1, 1};
+  if (!c.plain) {
+    d_cidx_e.upload(c.h_cidx_e);
+    d_cidx_t.upload(c.h_cidx_t);
+  }
   for (size_t bi = 0; bi < plan.parts.size(); ++bi) {
     const Part& q = plan.parts[bi];
     const PcBlk& pb = c.pc_blocks[bi];
@@ -528,6 +635,9 @@ void build_precond(Ctx& c, hipStream_t s) {
     const int n = ob.n, ld = (n + 1) & ~1;
     const int64_t t0 = r.obj_tri_off[i], nt = r.obj_tri_off[i + 1] - t0;
     const int64_t E = int64_t(q.ext_e.size()), T = int64_t(q.ext_t.size()), S = E + T;
+    // element-wise kernels over S x S and n x E use one work-item per entry (< 2^32 per dispatch)
+    SLIM_REQUIRE(S * S < (int64_t(1) << 32) && int64_t(n) * E < (int64_t(1) << 32), SLIM_E_UNSUPPORTED,
+                 "preconditioner block of " + std::to_string(S) + " unknowns is too large (cap it with precond_cap)");
     // local index lists and row maps
     std::vector<int32_t> Eloc(static_cast<size_t>(E)), Tloc(static_cast<size_t>(T));
     std::vector<int32_t> em(static_cast<size_t>(n), -1), tm(static_cast<size_t>(nt), -1);
@@ -558,6 +668,48 @@ void build_precond(Ctx& c, hipStream_t s) {
     L.near_pairs = dpairs.as<int32_t>();
     L.n_near_pairs = int64_t(pairs.size() / 2);
     launch_assemble(L, s);
+    if (!c.plain) {
+      // the conductor's far pairs as the AIM operator represents them (grid part only)
+      if (gtab_obj != i) {
+        int lo3[3], hi3[3];
+        for (int k = 0; k < 3; ++k) { lo3[k] = 1 << 30; hi3[k] = -(1 << 30); }
+        auto span = [&](const std::vector<int32_t>& cidx, int64_t b0, int64_t b1) {
+          for (int64_t q2 = b0; q2 < b1; ++q2)
+            for (int k = 0; k < 3; ++k) {
+              lo3[k] = std::min(lo3[k], cidx[3 * size_t(q2) + k]);
+              hi3[k] = std::max(hi3[k], cidx[3 * size_t(q2) + k]);
+            }
+        };
+        span(c.h_cidx_e, ob.e0, ob.e0 + n);
+        span(c.h_cidx_t, t0, t0 + nt);
+        for (int k = 0; k < 3; ++k) { gl[k] = -(hi3[k] - lo3[k]) - 2; gD[k] = 2 * (hi3[k] - lo3[k]) + 5; }
+        const int64_t ntab = int64_t(gD[0]) * gD[1] * gD[2];
+        if (size_t(ntab) * 16 > gtab.bytes) gtab.alloc(size_t(ntab) * 16);
+        hipLaunchKernelGGL(k_pc_gtab, dim3(nb256(ntab)), dim3(256), 0, s, gtab.as<double2>(), gl[0], gl[1], gl[2], gD[0],
+                           gD[1], gD[2], c.grid.h[0], c.grid.h[1], c.grid.h[2], c.k0);
+        SLIM_HIP(hipGetLastError());
+        gtab_obj = i;
+      }
+      FarArgs fa2{};
+      fa2.gtab = gtab.as<double2>();
+      fa2.lx = gl[0]; fa2.ly = gl[1]; fa2.lz = gl[2]; fa2.Dx = gD[0]; fa2.Dy = gD[1];
+      fa2.near_cheb = c.near_cheb;
+      if (E > 0) {
+        fa2.L = la.as<double2>(); fa2.ld = E; fa2.rows = E; fa2.cols = n;
+        fa2.row_local = dE.as<int32_t>(); fa2.base = ob.e0;
+        fa2.cidx = d_cidx_e.as<int32_t>(); fa2.w = c.d_we_w64.as<double>(); fa2.ncomp = 3;
+        hipLaunchKernelGGL(k_pc_far_grid, dim3(nb256(E * n)), dim3(256), 0, s, fa2);
+        SLIM_HIP(hipGetLastError());
+      }
+      if (nR > 0) {
+        dR.upload(R);
+        fa2.L = lp.as<double2>(); fa2.ld = nR; fa2.rows = nR; fa2.cols = nt;
+        fa2.row_local = dR.as<int32_t>(); fa2.base = int(t0);
+        fa2.cidx = d_cidx_t.as<int32_t>(); fa2.w = c.d_wt_w64.as<double>(); fa2.ncomp = 1;
+        hipLaunchKernelGGL(k_pc_far_grid, dim3(nb256(nR * nt)), dim3(256), 0, s, fa2);
+        SLIM_HIP(hipGetLastError());
+      }
+    }
     // W = L_A[E,:] (I - M)[:, E]  (a part may own triangles only)
     if (E > 0) {
       hipLaunchKernelGGL(k_pc_mcols, dim3(nb256(int64_t(n) * E)), dim3(256), 0, s, c.d_hi.as<float2>(),
@@ -582,12 +734,24 @@ void build_precond(Ctx& c, hipStream_t s) {
     fa.B = B.as<double2>();
     hipLaunchKernelGGL(k_pc_fill, dim3(nb256(S * S)), dim3(256), 0, s, fa);
     SLIM_HIP(hipGetLastError());
+    // 1-norm of the block (for its condition estimate)
+    hipLaunchKernelGGL(k_pc_colsum, dim3(unsigned(S)), dim3(256), 0, s, B.as<double2>(), S, colsum.as<double>());
+    SLIM_HIP(hipGetLastError());
+    std::vector<double> cs(static_cast<size_t>(S));
+    SLIM_HIP(hipMemcpyAsync(cs.data(), colsum.p, size_t(S) * 8, hipMemcpyDeviceToHost, s));
+    SLIM_HIP(hipStreamSynchronize(s));
+    const double nb1 = *std::max_element(cs.begin(), cs.end());
     // FP64 LU and inverse of the block; keep the owned rows in complex64
     SLIM_ROCP(rocsolver_zgetrf(h, int(S), int(S), B.as<rocblas_double_complex>(), int(S), ipiv.as<rocblas_int>(),
                                info.as<rocblas_int>() + bi));
     hipLaunchKernelGGL(k_pc_eye, dim3(nb256(S * S)), dim3(256), 0, s, X.as<double2>(), S);
     SLIM_HIP(hipGetLastError());
     lu_solve(h, int(S), B.as<double>(), ipiv.as<rocblas_int>(), X.as<double>(), s);
+    hipLaunchKernelGGL(k_pc_colsum, dim3(unsigned(S)), dim3(256), 0, s, X.as<double2>(), S, colsum.as<double>());
+    SLIM_HIP(hipGetLastError());
+    SLIM_HIP(hipMemcpyAsync(cs.data(), colsum.p, size_t(S) * 8, hipMemcpyDeviceToHost, s));
+    SLIM_HIP(hipStreamSynchronize(s));
+    c.pc_cond.push_back(nb1 * *std::max_element(cs.begin(), cs.end()));
     hipLaunchKernelGGL(k_pc_pack, dim3(nb256(int64_t(pb.n_own) * pb.ld)), dim3(256), 0, s, X.as<double2>(), S,
                        dpos.as<int32_t>(), pb.n_own, pb.ld, c.d_pc.as<float2>() + pb.off);
     SLIM_HIP(hipGetLastError());
@@ -608,6 +772,19 @@ void build_precond(Ctx& c, hipStream_t s) {
     SLIM_HIP(hipMemcpy(h_info.data(), info.p, h_info.size() * sizeof(rocblas_int), hipMemcpyDeviceToHost));
   for (size_t k = 0; k < h_info.size(); ++k)
     SLIM_REQUIRE(h_info[k] == 0, SLIM_E_NUMERIC, "singular preconditioner block " + std::to_string(k));
+  if (o.verbose && !c.pc_cond.empty()) {
+    std::vector<size_t> idx(c.pc_cond.size());
+    std::iota(idx.begin(), idx.end(), size_t(0));
+    std::sort(idx.begin(), idx.end(), [&](size_t a, size_t b) { return c.pc_cond[a] > c.pc_cond[b]; });
+    int over = 0;
+    for (double k : c.pc_cond) over += k * 0x1p-24 > 0.1;
+    std::fprintf(stderr, "[slim build] preconditioner blocks with cond_1 * 2^-24 > 0.1: %d of %zu; largest:", over,
+                 c.pc_cond.size());
+    for (size_t k = 0; k < std::min<size_t>(8, idx.size()); ++k)
+      std::fprintf(stderr, " %.2e (size %d)", c.pc_cond[idx[k]], c.pc_blocks[idx[k]].n_ext);
+    std::fprintf(stderr, "\n");
+    std::fflush(stderr);
+  }
   pc_pack_tiles(c, c.slots > 0 ? c.slots : 1024);
   c.pc_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
   c.pc_built = true;

@@ -468,9 +468,14 @@ void launch_assemble(const AsmLaunch& L, hipStream_t s) {
   if (wk) hipLaunchKernelGGL(k_assemble_far<true>, grid, dim3(256), 0, s, g);
   else hipLaunchKernelGGL(k_assemble_far<false>, grid, dim3(256), 0, s, g);
   SLIM_HIP(hipGetLastError());
-  if (L.n_near_pairs > 0) {
-    if (wk) hipLaunchKernelGGL(k_assemble_near<true>, dim3(unsigned(L.n_near_pairs)), dim3(64), 0, s, g, L.near_pairs, L.n_near_pairs);
-    else hipLaunchKernelGGL(k_assemble_near<false>, dim3(unsigned(L.n_near_pairs)), dim3(64), 0, s, g, L.near_pairs, L.n_near_pairs);
+  // one 64-lane workgroup per candidate pair, at most 2^25 per launch (a dispatch
+  // holds fewer than 2^32 work-items)
+  const int64_t chunk = int64_t(1) << 25;
+  for (int64_t lo = 0; lo < L.n_near_pairs; lo += chunk) {
+    const int64_t np = std::min(chunk, L.n_near_pairs - lo);
+    const int32_t* pp = L.near_pairs + 2 * lo;
+    if (wk) hipLaunchKernelGGL(k_assemble_near<true>, dim3(unsigned(np)), dim3(64), 0, s, g, pp, np);
+    else hipLaunchKernelGGL(k_assemble_near<false>, dim3(unsigned(np)), dim3(64), 0, s, g, pp, np);
     SLIM_HIP(hipGetLastError());
   }
 }
@@ -547,7 +552,9 @@ __global__ void __launch_bounds__(64) k_near_Lphi(NearArgs g) {
 
 void launch_near_entries(const NearArgs& g, bool rwg, hipStream_t s) {
   if (g.nnz == 0) return;
-  const int64_t chunk = int64_t(1) << 30;
+  // one 64-lane workgroup per non-zero; a dispatch holds fewer than 2^32 work-items
+  // in total, so at most 2^25 workgroups go into one launch
+  const int64_t chunk = int64_t(1) << 25;
   for (int64_t lo = 0; lo < g.nnz; lo += chunk) {
     NearArgs h = g;
     h.rows += lo; h.cols += lo; h.out += 2 * lo;

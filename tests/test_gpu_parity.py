@@ -165,7 +165,7 @@ def test_mesh_and_state_errors(c1_mesh):
     assert ei.value.code == 4
 
 
-@pytest.mark.parametrize("N", [(16, 16, 16), (32, 8, 16)])
+@pytest.mark.parametrize("N", [(16, 16, 16), (32, 8, 16), (256, 8, 8), (8, 256, 16), (16, 8, 256), (128, 16, 8), (512, 8, 8)])
 def test_grid_convolution_parity(N):
     """The FFT convolution H of eq. (11) alone (pruned passes, fused spectrum multiply)
     against the oracle's numpy FFT on the same (anisotropic) grid."""

@@ -144,3 +144,48 @@ def test_precond_errors():
     with pytest.raises(slim.SlimError) as e:
         context(m, freq=10e9, grid=(0, 0, 0), precond_cap=64, precond_budget=1000)
     assert e.value.code == 4
+
+
+from tests.test_gpu_parity import boxes_case, _oracle_aim_parts  # noqa: E402,F401  (fixture and oracle product)
+
+
+@pytest.fixture(scope="module")
+def aim_system(boxes_case):
+    """Dense equilibrated matrix of the oracle's AIM system (columns of its product)."""
+    m, g, ph, op, Ix, D, inner = boxes_case
+    n = g.n_e + g.n_t
+    A = np.zeros((n, n), dtype=complex)
+    for j in range(n):
+        e = np.zeros(n, dtype=complex)
+        e[j] = 1.0
+        A[:, j] = _oracle_aim_parts(boxes_case, e)['y']
+    s = row_scaling(g.n_e, g.n_t, g.length.mean())
+    return s[:, None] * A
+
+
+@pytest.mark.parametrize("cap,overlap", [(0, 2), (90, 2)])
+def test_apply_matches_oracle_aim(boxes_case, aim_system, cap, overlap):
+    """With the AIM operator the blocks are the conductor's part of that operator:
+    exact interactions on near pairs, grid interactions on far pairs."""
+    import torch
+    m, g = boxes_case[0], boxes_case[1]
+    print("case: small_boxes AIM apply cap", cap, flush=True)
+    ctx, lay = context(m, freq=10e9, grid=(16, 16, 16), precond_cap=cap, precond_overlap=overlap,
+                       precond_budget=1 << 33)
+    blocks = opc.build(aim_system, opc.partition(g, cap=cap, overlap=overlap))
+    if cap:
+        assert len(blocks) > g.n_obj
+    smax = max(len(b.ext) for b in blocks)
+    v = random_complex(aim_system.shape[0], 2)
+    z_ref = opc.apply(blocks, v)
+    bound = np.zeros(aim_system.shape[0])
+    for b in blocks:
+        bound[b.ext[b.own_pos]] = np.abs(b.rows) @ np.abs(v[b.ext])
+    vt = torch.tensor(v, device='cuda')
+    zt = torch.full_like(vt, float('nan'))
+    ctx.precond_apply(vt, zt)
+    torch.cuda.synchronize()
+    z = zt.cpu().numpy()
+    err = np.linalg.norm(z - z_ref)
+    assert err <= 2 * (smax + 3) * U32 * np.linalg.norm(bound), (err, np.linalg.norm(bound))
+    assert err <= 1e-4 * np.linalg.norm(z_ref)

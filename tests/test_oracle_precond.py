@@ -50,13 +50,15 @@ def test_partition_invariants(boxes, cap, overlap):
         ne_b = np.sum(b.ext < g.n_e)
         assert np.all(np.diff(b.ext[:ne_b]) > 0) and np.all(np.diff(b.ext[ne_b:]) > 0)
         assert np.all(b.ext[ne_b:] >= g.n_e)
-        # an extended edge has its T+ triangle in the extended set
+        # an extended edge has both triangles in the extended set: no current
+        # crosses the boundary of the block
         ext_t = b.ext[ne_b:] - g.n_e
-        assert np.all(np.isin(g.tplus[b.ext[:ne_b]], ext_t))
+        assert np.all(np.isin(g.tplus[b.ext[:ne_b]], ext_t)) and np.all(np.isin(g.tminus[b.ext[:ne_b]], ext_t))
+        # and every edge of the object with both triangles there is in the block
+        inside = np.nonzero(np.isin(g.tplus, ext_t) & np.isin(g.tminus, ext_t))[0]
+        assert np.array_equal(inside, b.ext[:ne_b])
         if cap > 0 and len(b.own_pos) != len(b.ext):
             assert len(b.own_pos) <= cap
-        if overlap == 0:
-            assert len(b.own_pos) == len(b.ext)
     assert np.all(owner >= 0), "an unknown is owned by no block"
     # conductors within the cap stay whole
     for i in range(g.n_obj):
@@ -119,16 +121,20 @@ def test_identity_on_matrices_block_diagonal_over_owned_sets(boxes, cap, overlap
     assert np.abs(X - np.eye(n)).max() <= 1e-10
 
 
-def test_overlap_differs_from_block_jacobi_on_coupled_matrix(boxes):
-    """With coupling across parts, overlap changes the result (the extension is used)."""
+def test_overlap_differs_on_coupled_matrix(boxes):
+    """With coupling across parts, a wider overlap changes the result (the extension
+    is used); overlap 0 is taken as one ring, since an owned edge needs both its
+    triangles in the block."""
     g = boxes
     n = g.n_e + g.n_t
     rng = np.random.default_rng(3)
     A = rng.standard_normal((n, n)) * 0.01 + np.eye(n) * 3.0
     v = rng.standard_normal(n) + 0j
     z0 = precond.apply(precond.build(A, precond.partition(g, 120, 0)), v)
+    z1 = precond.apply(precond.build(A, precond.partition(g, 120, 1)), v)
     z2 = precond.apply(precond.build(A, precond.partition(g, 120, 2)), v)
-    assert np.linalg.norm(z0 - z2) > 1e-6 * np.linalg.norm(z0)
+    assert np.array_equal(z0, z1)
+    assert np.linalg.norm(z1 - z2) > 1e-6 * np.linalg.norm(z1)
 
 
 def test_fgmres_matches_lu_with_rounded_preconditioner():
