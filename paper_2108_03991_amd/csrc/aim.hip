@@ -267,6 +267,17 @@ __global__ void k_to_c64(const double* in, float* out, int64_t n2) {
   if (i < n2) out[i] = float(in[i]);
 }
 
+// octant [0, Nz] x [0, Ny] x [0, Nx] of the (2N)^3 spectrum, complex128 and complex64
+__global__ void k_spectrum_octant(const double2* full, int Nx, int Ny, int Nz, double2* o128, float2* o64) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t X1 = Nx + 1, Y1 = Ny + 1;
+  if (i >= X1 * Y1 * (Nz + 1)) return;
+  const int64_t x = i % X1, y = (i / X1) % Y1, z = i / (X1 * Y1);
+  const double2 v = full[(z * (2 * Ny) + y) * (2 * Nx) + x];
+  o128[i] = v;
+  o64[i] = make_float2(float(v.x), float(v.y));
+}
+
 // Circulant Green's function on the (2N)^3 grid, index order [z][y][x].
 __global__ void k_circulant(double* G, int Nx, int Ny, int Nz, double hx, double hy, double hz, double k0) {
   const int64_t X2 = 2 * Nx, Y2 = 2 * Ny, Z2 = 2 * Nz;
@@ -434,11 +445,15 @@ void build_aim(Ctx& c, hipStream_t s) {
     fft_forward_3d_c128(c, g128.as<double>(), s);
     hipLaunchKernelGGL(k_scale_real, dim3(nblk(2 * full)), dim3(256), 0, s, g128.as<double>(), 2 * full, 1.0 / double(full));
     SLIM_HIP(hipGetLastError());
-    c.d_ghat64.alloc(size_t(full) * 8);
-    hipLaunchKernelGGL(k_to_c64, dim3(nblk(2 * full)), dim3(256), 0, s, g128.as<double>(), c.d_ghat64.as<float>(), 2 * full);
+    // The kernel is even in every coordinate, so is its spectrum: keep the octant
+    // k_c in [0, N_c] (the z pass reads it with mirrored indices)
+    const int64_t oct = int64_t(G.N[0] + 1) * (G.N[1] + 1) * (G.N[2] + 1);
+    c.d_ghat128.alloc(size_t(oct) * 16);
+    c.d_ghat64.alloc(size_t(oct) * 8);
+    hipLaunchKernelGGL(k_spectrum_octant, dim3(nblk(oct)), dim3(256), 0, s, g128.as<double2>(), G.N[0], G.N[1], G.N[2],
+                       c.d_ghat128.as<double2>(), c.d_ghat64.as<float2>());
     SLIM_HIP(hipGetLastError());
     SLIM_HIP(hipStreamSynchronize(s));
-    c.d_ghat128 = std::move(g128);
   }
   // ---- FFT work arrays: 4 components (x, y, z, rho), sized for complex128 ----
   const int64_t N3 = G.nodes();

@@ -126,8 +126,9 @@ struct PassArgs {
   int n1, n2;            // line counts along the two outer indices
   int n_in, n_out;       // elements read (others zero) / written per line
   const void* tw;        // L twiddles e^{-2 pi i m / L}
-  const void* mul;       // spectrum for the fused pass
-  int64_t mul_e, mul_o1, mul_o2;
+  const void* mul;       // spectrum octant for the fused pass: index k of a line of length 2h is
+  int64_t mul_e, mul_o1, mul_o2;   // read at min(k, 2h - k) (the spectrum is even)
+  int h_e, h_o1, h_o2;
   int64_t comp_in, comp_out;   // component strides (blockIdx.z)
 };
 
@@ -169,7 +170,9 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_pass(PassArgs a) {
       int b, i;
       if (CONTIG) { b = e / L; i = e % L; } else { b = e % W; i = e / W; }
       const int o1 = g1 + b;
-      if (o1 < a.n1) lds[pidx<L>(b, i)] = cmul(lds[pidx<L>(b, i)], G[o1 * a.mul_o1 + o2 * a.mul_o2 + int64_t(i) * a.mul_e]);
+      const int m1 = o1 <= a.h_o1 ? o1 : 2 * a.h_o1 - o1, m2 = o2 <= a.h_o2 ? o2 : 2 * a.h_o2 - o2,
+                me = i <= a.h_e ? i : 2 * a.h_e - i;
+      if (o1 < a.n1) lds[pidx<L>(b, i)] = cmul(lds[pidx<L>(b, i)], G[m1 * a.mul_o1 + m2 * a.mul_o2 + int64_t(me) * a.mul_e]);
     }
     __syncthreads();
     fft_batch<T, L, ELEMS, true>(lds, tw);
@@ -293,7 +296,8 @@ void aim_convolve(Ctx& c, bool fp64, int ncomp, hipStream_t s) {
     a.in_e = a.out_e = int64_t(X2) * Y2; a.in_o1 = a.out_o1 = 1; a.in_o2 = a.out_o2 = X2;
     a.n1 = X2; a.n2 = Y2; a.n_in = Nz; a.n_out = Nz;
     a.mul = fp64 ? c.d_ghat128.p : c.d_ghat64.p;
-    a.mul_e = int64_t(X2) * Y2; a.mul_o1 = 1; a.mul_o2 = X2;
+    a.mul_e = int64_t(Nx + 1) * (Ny + 1); a.mul_o1 = 1; a.mul_o2 = Nx + 1;
+    a.h_e = Nz; a.h_o1 = Nx; a.h_o2 = Ny;
     a.comp_in = a.comp_out = 4 * N3;
     a.tw = tw + tw_off(c, 2);
     launch_pass_L<T, false, 2>(Z2, a, ncomp, s);
