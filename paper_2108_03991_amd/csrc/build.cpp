@@ -168,6 +168,7 @@ Ctx::~Ctx() {
   if (ev_fork) (void)hipEventDestroy(ev_fork);
   if (ev_join) (void)hipEventDestroy(ev_join);
   if (s_aux) (void)hipStreamDestroy(s_aux);
+  if (s_phi) (void)hipStreamDestroy(s_phi);
 }
 
 static void build_internal(Ctx& c, hipStream_t s) {
@@ -363,6 +364,7 @@ void build_all(Ctx& c, const slim_build_opts& o) {
   c.d_a.alloc(size_t(r.n_e) * 16);
   c.d_phi.alloc(size_t(r.n_t) * 16);
   if (!c.s_aux) SLIM_HIP(hipStreamCreateWithFlags(&c.s_aux, hipStreamNonBlocking));
+  if (!c.s_phi) SLIM_HIP(hipStreamCreateWithFlags(&c.s_phi, hipStreamNonBlocking));
   if (!c.ev_fork) SLIM_HIP(hipEventCreateWithFlags(&c.ev_fork, hipEventDisableTiming));
   if (!c.ev_join) SLIM_HIP(hipEventCreateWithFlags(&c.ev_join, hipEventDisableTiming));
 
@@ -373,7 +375,8 @@ void build_all(Ctx& c, const slim_build_opts& o) {
     c.slots = o.slots;
     pack_tiles(c, o.sched_mode);
   } else {
-    // autotune the number of persistent workgroups of the internal kernel
+    // autotune the number of persistent workgroups of the internal kernel on the
+    // whole mixed product: fewer workgroups leave room for the concurrent pulse path
     int cus = 256;
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, c.device) == hipSuccess && prop.multiProcessorCount > 0) cus = prop.multiProcessorCount;
@@ -384,8 +387,8 @@ void build_all(Ctx& c, const slim_build_opts& o) {
     for (int per_cu : {2, 4, 8}) {
       c.slots = per_cu * cus;
       pack_tiles(c, o.sched_mode == 1 ? 0 : o.sched_mode);
-      const double ms = time_internal(c, 3);
-      if (o.verbose) std::fprintf(stderr, "[slim build] autotune: %d slots -> %.3f ms\n", c.slots, ms);
+      const double ms = time_product(c, 3);
+      if (o.verbose) std::fprintf(stderr, "[slim build] autotune: %d slots -> %.3f ms per product\n", c.slots, ms);
       if (ms < best_ms) { best_ms = ms; best = c.slots; }
     }
     c.slots = best;

@@ -122,6 +122,7 @@ struct Ctx {
   std::vector<std::pair<GraphKey, hipGraphExec_t>> graphs;
   void drop_graphs();
   hipStream_t s_aux = nullptr;
+  hipStream_t s_phi = nullptr;          // pulse (phi) path of the product, concurrent with the internal blocks
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 
   // ---- per-stage timing ----
@@ -148,6 +149,7 @@ void matvec(Ctx& c, slim_prec prec, const void* x, void* y, void* e_out, void* g
 void internal_apply(Ctx& c, slim_prec prec, const void* H, void* e, void* g, hipStream_t s, bool h_is_c128);
 void matvec_graph(Ctx& c, slim_prec prec, const void* x, void* y, hipStream_t s);
 double time_internal(Ctx& c, int reps);   // ms per launch of the mixed internal kernel
+double time_product(Ctx& c, int reps);    // ms per mixed product
 void launch_cast_c128_to_c64(const void* in, void* out, int64_t n, hipStream_t s);
 void launch_cast_c64_to_c128(const void* in, void* out, int64_t n, hipStream_t s);
 void launch_pack_block(const double* Zcm, const double* Mcm, int n, Cplx<float>* hi, Cplx<float>* lo, hipStream_t s);
@@ -158,7 +160,7 @@ void launch_pack_dense(const double* Acm, int64_t rows, int64_t cols, Cplx<float
 // fft.hip
 void fft_init_twiddles(Ctx& c);
 void fft_forward_3d_c128(Ctx& c, double* data_full, hipStream_t s);   // full (2N)^3 in place (build)
-void aim_convolve(Ctx& c, bool fp64, int ncomp, hipStream_t s);        // oct_in -> oct_out, ncomp components
+void aim_convolve(Ctx& c, bool fp64, int ncomp, hipStream_t s, int comp0 = 0);   // oct_in -> oct_out
 // sched.cpp
 void pack_tiles(Ctx& c, int mode);
 // precond.hip

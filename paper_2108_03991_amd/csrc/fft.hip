@@ -258,17 +258,19 @@ void fft_forward_3d_c128(Ctx& c, double* data, hipStream_t s) {
   launch_pass_L<double, false, 0>(Z2, a, 1, s);
 }
 
-// oct_in (ncomp x N^3, [z][y][x]) -> oct_out, each convolved with the grid Green's function.
-void aim_convolve(Ctx& c, bool fp64, int ncomp, hipStream_t s) {
+// Components [comp0, comp0 + ncomp) of oct_in (4 x N^3, [z][y][x]) -> oct_out, each
+// convolved with the grid Green's function.  Distinct components use disjoint
+// parts of every work array, so two calls on different components may run
+// concurrently.
+void aim_convolve(Ctx& c, bool fp64, int ncomp, hipStream_t s, int comp0) {
   const int Nx = c.grid.N[0], Ny = c.grid.N[1], Nz = c.grid.N[2];
   const int X2 = 2 * Nx, Y2 = 2 * Ny, Z2 = 2 * Nz;
   const int64_t N3 = c.grid.nodes();
   const size_t esz = fp64 ? 16 : 8;
-  char* oin = reinterpret_cast<char*>(fp64 ? c.d_oct_in.p : c.d_oct_in32.p);
-  char* oout = reinterpret_cast<char*>(c.d_oct_out.p);
-  char* x1 = reinterpret_cast<char*>(c.d_x1.p);
-  char* x2 = reinterpret_cast<char*>(c.d_x2.p);
-  (void)esz;
+  char* oin = reinterpret_cast<char*>(fp64 ? c.d_oct_in.p : c.d_oct_in32.p) + size_t(comp0) * N3 * esz;
+  char* oout = reinterpret_cast<char*>(c.d_oct_out.p) + size_t(comp0) * N3 * esz;
+  char* x1 = reinterpret_cast<char*>(c.d_x1.p) + size_t(comp0) * 2 * N3 * esz;
+  char* x2 = reinterpret_cast<char*>(c.d_x2.p) + size_t(comp0) * 4 * N3 * esz;
   auto run = [&](auto tag) {
     using T = decltype(tag);
     const C2<T>* tw = reinterpret_cast<const C2<T>*>(fp64 ? c.d_tw128.p : c.d_tw64.p);

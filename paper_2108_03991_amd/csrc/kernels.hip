@@ -456,11 +456,36 @@ void matvec_t(Ctx& c, const void* x, void* y, void* e_out, void* g_out, void* a_
   double2* Y = reinterpret_cast<double2*>(y);
   if (c.prof_on) c.prof_calls++;
   auto mark = [&](int st) { if (c.prof_on) c.prof_mark(st, s); };
+  const double inv_eta0 = 1.0 / eta0();
+  // The pulse path (projection of B c0rho, its convolution, W and L_phi,NR) does
+  // not depend on the internal blocks: without per-stage timing it runs on a
+  // second stream, concurrently with them, and joins before the RWG rows.
+  const bool aim = !c.plain;
+  const bool overlap = aim && !c.prof_on && c.s_phi;
+  const int64_t N3 = aim ? c.grid.nodes() : 0;
+  void* oct_in = F64 ? c.d_oct_in.p : c.d_oct_in32.p;
+  const int Nx = c.grid.N[0], NxNy = c.grid.N[0] * c.grid.N[1];
+  auto pulse_path = [&](hipStream_t st) {
+    hipLaunchKernelGGL(k_project<F64>, dim3(nblk(c.n_pt_nodes)), dim3(256), 0, st, nullptr, nullptr, nullptr, nullptr,
+                       int64_t(0), c.d_pt_node.as<int32_t>(), c.d_pt_ptr.as<int32_t>(), c.d_pt_idx.as<int32_t>(),
+                       F64 ? c.d_pt_w64.p : c.d_pt_w32.p, c.n_pt_nodes, nullptr, rho, oct_in, N3);
+    SLIM_HIP(hipGetLastError());
+    aim_convolve(c, F64, 1, st, 3);
+    hipLaunchKernelGGL(k_phi<F64>, dim3(nblk(nt, 4)), dim3(256), 0, st, c.d_wt_base.as<int32_t>(),
+                       F64 ? c.d_wt_w64.p : c.d_wt_w32.p, c.d_oct_out.p, N3, Nx, NxNy, c.d_nP_ptr.as<int64_t>(),
+                       c.d_nP_col.as<int32_t>(), F64 ? c.d_nP_v128.p : c.d_nP_v64.p, rho, c.d_phi.p, nt);
+    SLIM_HIP(hipGetLastError());
+  };
+  if (overlap) {
+    SLIM_HIP(hipEventRecord(c.ev_fork, s));
+    SLIM_HIP(hipStreamWaitEvent(c.s_phi, c.ev_fork, 0));
+    pulse_path(c.s_phi);
+    SLIM_HIP(hipEventRecord(c.ev_join, c.s_phi));
+  }
   // A1 + A2
   mark(0);
   internal_launch<F64>(c, X, c.d_e.p, c.d_j.p, g_out ? c.d_g.p : nullptr, s);
   mark(0);
-  const double inv_eta0 = 1.0 / eta0();
   if (c.plain) {
     hipLaunchKernelGGL(k_dense_gemv<F64>, dim3(nblk(nt, 4)), dim3(256), 0, s, c.d_Lphi_hi.as<float2>(),
                        c.d_Lphi_lo.as<float2>(), nt, rho, c.d_area.as<double>(), c.d_phi.p);
@@ -472,25 +497,26 @@ void matvec_t(Ctx& c, const void* x, void* y, void* e_out, void* g_out, void* a_
                        c.d_tplus.as<int32_t>(), c.d_tminus.as<int32_t>(), c.d_len.as<double>(),
                        c.d_ix_col.as<int32_t>(), c.d_ix_val.as<double>(), c.k0, inv_eta0, nullptr, Y, ne);
   } else {
-    const int64_t N3 = c.grid.nodes();
-    void* oct_in = F64 ? c.d_oct_in.p : c.d_oct_in32.p;
     mark(1);
-    hipLaunchKernelGGL(k_project<F64>, dim3(nblk(c.n_pe_nodes + c.n_pt_nodes)), dim3(256), 0, s,
+    hipLaunchKernelGGL(k_project<F64>, dim3(nblk(c.n_pe_nodes + (overlap ? 0 : c.n_pt_nodes))), dim3(256), 0, s,
                        c.d_pe_node.as<int32_t>(), c.d_pe_ptr.as<int32_t>(), c.d_pe_idx.as<int32_t>(),
                        F64 ? c.d_pe_w64.p : c.d_pe_w32.p, c.n_pe_nodes, c.d_pt_node.as<int32_t>(),
                        c.d_pt_ptr.as<int32_t>(), c.d_pt_idx.as<int32_t>(), F64 ? c.d_pt_w64.p : c.d_pt_w32.p,
-                       c.n_pt_nodes, c.d_j.p, rho, oct_in, N3);
+                       overlap ? int64_t(0) : c.n_pt_nodes, c.d_j.p, rho, oct_in, N3);
     SLIM_HIP(hipGetLastError());
     mark(1);
     mark(2);
-    aim_convolve(c, F64, 4, s);
+    aim_convolve(c, F64, overlap ? 3 : 4, s);
     mark(2);
-    const int Nx = c.grid.N[0], NxNy = c.grid.N[0] * c.grid.N[1];
     mark(3);
-    hipLaunchKernelGGL(k_phi<F64>, dim3(nblk(nt, 4)), dim3(256), 0, s, c.d_wt_base.as<int32_t>(),
-                       F64 ? c.d_wt_w64.p : c.d_wt_w32.p, c.d_oct_out.p, N3, Nx, NxNy, c.d_nP_ptr.as<int64_t>(),
-                       c.d_nP_col.as<int32_t>(), F64 ? c.d_nP_v128.p : c.d_nP_v64.p, rho, c.d_phi.p, nt);
-    SLIM_HIP(hipGetLastError());
+    if (overlap) {
+      SLIM_HIP(hipStreamWaitEvent(s, c.ev_join, 0));
+    } else {
+      hipLaunchKernelGGL(k_phi<F64>, dim3(nblk(nt, 4)), dim3(256), 0, s, c.d_wt_base.as<int32_t>(),
+                         F64 ? c.d_wt_w64.p : c.d_wt_w32.p, c.d_oct_out.p, N3, Nx, NxNy, c.d_nP_ptr.as<int64_t>(),
+                         c.d_nP_col.as<int32_t>(), F64 ? c.d_nP_v128.p : c.d_nP_v64.p, rho, c.d_phi.p, nt);
+      SLIM_HIP(hipGetLastError());
+    }
     mark(3);
     mark(4);
     hipLaunchKernelGGL((k_rows_A<F64, true>), dim3(nblk(ne, 4)), dim3(256), 0, s, c.d_we_base.as<int32_t>(),
@@ -597,6 +623,29 @@ void matvec_graph(Ctx& c, slim_prec prec, const void* x, void* y, hipStream_t s)
     c.graphs.push_back({Ctx::GraphKey{int(prec), x, y}, exec});
   }
   SLIM_HIP(hipGraphLaunch(exec, s));
+}
+
+// ms per mixed product (on the library's stream, eager launches)
+double time_product(Ctx& c, int reps) {
+  hipStream_t s = c.s_aux;
+  const int64_t n = c.rwg.n_e + c.rwg.n_t;
+  DevBuf x, y;
+  x.alloc(size_t(n) * 16);
+  y.alloc(size_t(n) * 16);
+  SLIM_HIP(hipMemsetAsync(x.p, 0, x.bytes, s));
+  hipEvent_t a, b;
+  SLIM_HIP(hipEventCreate(&a));
+  SLIM_HIP(hipEventCreate(&b));
+  matvec(c, SLIM_MIXED, x.p, y.p, nullptr, nullptr, nullptr, nullptr, s);
+  SLIM_HIP(hipEventRecord(a, s));
+  for (int r = 0; r < reps; ++r) matvec(c, SLIM_MIXED, x.p, y.p, nullptr, nullptr, nullptr, nullptr, s);
+  SLIM_HIP(hipEventRecord(b, s));
+  SLIM_HIP(hipEventSynchronize(b));
+  float ms = 0.f;
+  SLIM_HIP(hipEventElapsedTime(&ms, a, b));
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  return double(ms) / reps;
 }
 
 double time_internal(Ctx& c, int reps) {
