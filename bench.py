@@ -236,7 +236,8 @@ def main():
     ctx = slim.Context(0)
     ctx.set_mesh(mesh.verts, mesh.tris, mesh.obj, mesh.n_obj)
     t0 = time.time()
-    lay = ctx.build(freq=freq, grid=grid, sched_mode=args.sched, verbose=1)
+    # the conductor-block preconditioner is only built for the solve
+    lay = ctx.build(freq=freq, grid=grid, sched_mode=args.sched, verbose=1, precond=0 if args.no_solve else 1)
     log("build: %.1f s, n_e %d n_t %d nnzA %d nnzP %d tiles %d slots %d" % (
         time.time() - t0, lay.n_e, lay.n_t, lay.nnz_near_A, lay.nnz_near_phi, lay.n_tiles, lay.slots))
     n = lay.n_sys
