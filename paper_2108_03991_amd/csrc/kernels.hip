@@ -248,38 +248,56 @@ __global__ void __launch_bounds__(256) k_internal(const float2* __restrict__ hi,
 // RWG list: S_c(node) = sum w_c j_n (c = x, y, z); pulse list: S_rho = sum (w A_t) c0rho_t.
 // ---------------------------------------------------------------------------
 template <bool F64>
-__global__ void k_project(const int32_t* pe_node, const int32_t* pe_ptr, const int32_t* pe_idx, const void* pe_w,
-                          int64_t n_pe, const int32_t* pt_node, const int32_t* pt_ptr, const int32_t* pt_idx,
-                          const void* pt_w, int64_t n_pt, const void* jv, const void* rhov, void* octv, int64_t N3) {
+__device__ __forceinline__ typename P<F64>::T group_sum8(typename P<F64>::T v) {
+#pragma unroll
+  for (int off = 4; off > 0; off >>= 1) v += __shfl_xor(v, off, 8);
+  return v;
+}
+
+// Eight lanes per occupied node stride its (basis, weight) list, so the list is
+// read in contiguous runs; the partial sums meet through lane shuffles.
+template <bool F64>
+__global__ void __launch_bounds__(256) k_project(const int32_t* pe_node, const int32_t* pe_ptr, const int32_t* pe_idx,
+                                                 const void* pe_w, int64_t n_pe, const int32_t* pt_node,
+                                                 const int32_t* pt_ptr, const int32_t* pt_idx, const void* pt_w,
+                                                 int64_t n_pt, const void* jv, const void* rhov, void* octv, int64_t N3) {
   using T = typename P<F64>::T;
   const T* we = reinterpret_cast<const T*>(pe_w);
   const T* wt = reinterpret_cast<const T*>(pt_w);
   const C2<T>* j = reinterpret_cast<const C2<T>*>(jv);
   const C2<T>* rho = reinterpret_cast<const C2<T>*>(rhov);
   C2<T>* oct = reinterpret_cast<C2<T>*>(octv);
-  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t i = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 3;
+  const int sub = threadIdx.x & 7;
   if (i < n_pe) {
-    T sx[2] = {0, 0}, sy[2] = {0, 0}, sz[2] = {0, 0};
-    for (int z = pe_ptr[i]; z < pe_ptr[i + 1]; ++z) {
+    T sx0 = 0, sx1 = 0, sy0 = 0, sy1 = 0, sz0 = 0, sz1 = 0;
+    for (int z = pe_ptr[i] + sub; z < pe_ptr[i + 1]; z += 8) {
       const C2<T> v = j[pe_idx[z]];
       const T w0 = we[3 * int64_t(z)], w1 = we[3 * int64_t(z) + 1], w2 = we[3 * int64_t(z) + 2];
-      sx[0] += w0 * v.x; sx[1] += w0 * v.y;
-      sy[0] += w1 * v.x; sy[1] += w1 * v.y;
-      sz[0] += w2 * v.x; sz[1] += w2 * v.y;
+      sx0 += w0 * v.x; sx1 += w0 * v.y;
+      sy0 += w1 * v.x; sy1 += w1 * v.y;
+      sz0 += w2 * v.x; sz1 += w2 * v.y;
     }
-    const int64_t node = pe_node[i];
-    oct[node] = {sx[0], sx[1]};
-    oct[N3 + node] = {sy[0], sy[1]};
-    oct[2 * N3 + node] = {sz[0], sz[1]};
+    sx0 = group_sum8<F64>(sx0); sx1 = group_sum8<F64>(sx1);
+    sy0 = group_sum8<F64>(sy0); sy1 = group_sum8<F64>(sy1);
+    sz0 = group_sum8<F64>(sz0); sz1 = group_sum8<F64>(sz1);
+    if (sub == 0) {
+      const int64_t node = pe_node[i];
+      oct[node] = {sx0, sx1};
+      oct[N3 + node] = {sy0, sy1};
+      oct[2 * N3 + node] = {sz0, sz1};
+    }
   } else if (i < n_pe + n_pt) {
     const int64_t k = i - n_pe;
-    T s[2] = {0, 0};
-    for (int z = pt_ptr[k]; z < pt_ptr[k + 1]; ++z) {
+    T s0 = 0, s1 = 0;
+    for (int z = pt_ptr[k] + sub; z < pt_ptr[k + 1]; z += 8) {
       const C2<T> v = rho[pt_idx[z]];
-      s[0] += wt[z] * v.x;
-      s[1] += wt[z] * v.y;
+      s0 += wt[z] * v.x;
+      s1 += wt[z] * v.y;
     }
-    oct[3 * N3 + pt_node[k]] = {s[0], s[1]};
+    s0 = group_sum8<F64>(s0);
+    s1 = group_sum8<F64>(s1);
+    if (sub == 0) oct[3 * N3 + pt_node[k]] = {s0, s1};
   }
 }
 
@@ -466,7 +484,7 @@ void matvec_t(Ctx& c, const void* x, void* y, void* e_out, void* g_out, void* a_
   void* oct_in = F64 ? c.d_oct_in.p : c.d_oct_in32.p;
   const int Nx = c.grid.N[0], NxNy = c.grid.N[0] * c.grid.N[1];
   auto pulse_path = [&](hipStream_t st) {
-    hipLaunchKernelGGL(k_project<F64>, dim3(nblk(c.n_pt_nodes)), dim3(256), 0, st, nullptr, nullptr, nullptr, nullptr,
+    hipLaunchKernelGGL(k_project<F64>, dim3(nblk(8 * c.n_pt_nodes)), dim3(256), 0, st, nullptr, nullptr, nullptr, nullptr,
                        int64_t(0), c.d_pt_node.as<int32_t>(), c.d_pt_ptr.as<int32_t>(), c.d_pt_idx.as<int32_t>(),
                        F64 ? c.d_pt_w64.p : c.d_pt_w32.p, c.n_pt_nodes, nullptr, rho, oct_in, N3);
     SLIM_HIP(hipGetLastError());
@@ -498,7 +516,7 @@ void matvec_t(Ctx& c, const void* x, void* y, void* e_out, void* g_out, void* a_
                        c.d_ix_col.as<int32_t>(), c.d_ix_val.as<double>(), c.k0, inv_eta0, nullptr, Y, ne);
   } else {
     mark(1);
-    hipLaunchKernelGGL(k_project<F64>, dim3(nblk(c.n_pe_nodes + (overlap ? 0 : c.n_pt_nodes))), dim3(256), 0, s,
+    hipLaunchKernelGGL(k_project<F64>, dim3(nblk(8 * (c.n_pe_nodes + (overlap ? 0 : c.n_pt_nodes)))), dim3(256), 0, s,
                        c.d_pe_node.as<int32_t>(), c.d_pe_ptr.as<int32_t>(), c.d_pe_idx.as<int32_t>(),
                        F64 ? c.d_pe_w64.p : c.d_pe_w32.p, c.n_pe_nodes, c.d_pt_node.as<int32_t>(),
                        c.d_pt_ptr.as<int32_t>(), c.d_pt_idx.as<int32_t>(), F64 ? c.d_pt_w64.p : c.d_pt_w32.p,
