@@ -173,13 +173,25 @@ def solve_study(ctx, lay, max_iter):
     n = lay.n_sys
     b = torch.zeros(n, dtype=torch.complex128, device="cuda")
     ctx.rhs_planewave((0.0, 0.0, -1.0), (1.0, 0.0, 0.0), b)
-    out = {"rhs": "plane wave, E0 = 1 V/m along x, travelling along -z", "tol": 1e-6, "restart": 100,
+    out = {"rhs": "plane wave, E0 = 1 V/m along x, travelling along -z", "tol": 1e-6, "restart": 100, "inner_tol": 1e-6,
            "precond": {"blocks": lay.precond_blocks, "entries": lay.precond_entries, "cap": lay.precond_cap}}
+    # the preconditioner apply on its own (HBM-bound GEMV over the stored complex64 rows)
+    v = torch.randn(n, dtype=torch.complex128, device="cuda")
+    zz = torch.zeros_like(v)
+    ctx.precond_apply(v, zz)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(10):
+        ctx.precond_apply(v, zz)
+    torch.cuda.synchronize()
+    dt_pc = (time.perf_counter() - t) / 10
+    out["precond"]["apply_ms"] = 1e3 * dt_pc
+    out["precond"]["apply_GBps"] = lay.precond_entries * 8 / dt_pc / 1e9
     sols = {}
     for name, prec in (("mixed", slim.SLIM_MIXED), ("fp64", slim.SLIM_FP64)):
         xs = torch.zeros_like(b)
         torch.cuda.synchronize()
-        info, ok = ctx.solve(b, xs, tol=1e-6, restart=100, max_iter=max_iter, prec=prec, inner_tol=1e-2)
+        info, ok = ctx.solve(b, xs, tol=1e-6, restart=100, max_iter=max_iter, prec=prec, inner_tol=1e-6)
         out[name] = {"seconds": info.seconds, "iterations": info.iterations, "outer": info.outer_steps,
                      "precond_applies": info.n_precond, "matvecs_mixed": info.n_matvec_mixed,
                      "matvecs_fp64": info.n_matvec_fp64, "rel_residual": info.rel_residual, "converged": bool(ok)}
