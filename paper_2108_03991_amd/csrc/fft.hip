@@ -1,7 +1,7 @@
 // Grid convolution H of eq. (11) by FFT on the zero-padded (2N)^3 grid.
 //
 // One pass transforms every line along one axis.  A workgroup stages a batch of
-// lines in LDS (8192 complex64 or 4096 complex128 elements), runs a Stockham
+// lines in LDS (4096 or 8192 complex64, 4096 complex128 elements), runs a Stockham
 // autosort FFT with radix-8/4/2 butterflies held in registers, and writes the
 // result back.  Passes of the convolution, per component (x, y, z, rho):
 //   x-fwd  (reads the N^3 octant, the upper half of each line is zero)
@@ -135,9 +135,14 @@ struct PassArgs {
 // MODE 0: forward, 1: inverse, 2: forward, multiply, inverse.
 // CONTIG: lines are contiguous (in_e == 1), batch = consecutive lines along o1;
 // otherwise the batch is W = ELEMS/L adjacent lines (o1 stride 1) for coalescing.
+// Batch size in elements: strided passes keep 16 adjacent complex64 lines (128-byte
+// segments per row of the batch); contiguous passes take half, so that more
+// workgroups fit the LDS of a compute unit.
+template <class T, bool CONTIG> constexpr int batch_elems() { return (sizeof(T) == 4 && !CONTIG) ? 8192 : 4096; }
+
 template <class T, int L, bool CONTIG, int MODE>
 __global__ void __launch_bounds__(kFftThreads) k_fft_pass(PassArgs a) {
-  constexpr int ELEMS = sizeof(T) == 4 ? 8192 : 4096;
+  constexpr int ELEMS = batch_elems<T, CONTIG>();
   constexpr int W = ELEMS / L;
   extern __shared__ unsigned char smem_raw[];
   C2<T>* lds = reinterpret_cast<C2<T>*>(smem_raw);
@@ -187,7 +192,7 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_pass(PassArgs a) {
 
 template <class T, bool CONTIG, int MODE>
 void launch_pass_L(int L, const PassArgs& a, int ncomp, hipStream_t s) {
-  constexpr int ELEMS = sizeof(T) == 4 ? 8192 : 4096;
+  constexpr int ELEMS = batch_elems<T, CONTIG>();
   const size_t shm = size_t((ELEMS / L) * (L + L / 8 + 1) + (sizeof(T) == 4 ? L : 0)) * sizeof(C2<T>);
   const int W = ELEMS / L;
   dim3 grid(unsigned((a.n1 + W - 1) / W), unsigned(a.n2), unsigned(ncomp));
