@@ -384,12 +384,18 @@ void build_all(Ctx& c, const slim_build_opts& o) {
     SLIM_HIP(hipStreamSynchronize(s));
     int best = 0;
     double best_ms = 1e300;
-    for (int per_cu : {2, 4, 8}) {
-      c.slots = per_cu * cus;
-      pack_tiles(c, o.sched_mode == 1 ? 0 : o.sched_mode);
-      const double ms = time_product(c, 3);
-      if (o.verbose) std::fprintf(stderr, "[slim build] autotune: %d slots -> %.3f ms per product\n", c.slots, ms);
-      if (ms < best_ms) { best_ms = ms; best = c.slots; }
+    std::vector<double> t_slot(3, 1e300);
+    const int per_cu_set[3] = {2, 4, 8};
+    for (int round = 0; round < 2; ++round)   // two interleaved rounds, best of each: less noise
+      for (int k = 0; k < 3; ++k) {
+        c.slots = per_cu_set[k] * cus;
+        pack_tiles(c, o.sched_mode == 1 ? 0 : o.sched_mode);
+        t_slot[k] = std::min(t_slot[k], time_product(c, 4));
+      }
+    for (int k = 0; k < 3; ++k) {
+      if (o.verbose)
+        std::fprintf(stderr, "[slim build] autotune: %d slots -> %.3f ms per product\n", per_cu_set[k] * cus, t_slot[k]);
+      if (t_slot[k] < best_ms) { best_ms = t_slot[k]; best = per_cu_set[k] * cus; }
     }
     c.slots = best;
     pack_tiles(c, o.sched_mode == 1 ? 0 : o.sched_mode);
