@@ -643,7 +643,8 @@ void matvec_graph(Ctx& c, slim_prec prec, const void* x, void* y, hipStream_t s)
   SLIM_HIP(hipGraphLaunch(exec, s));
 }
 
-// ms per mixed product (on the library's stream, eager launches)
+// ms per mixed product on the library's stream, through the path slim_matvec
+// takes (graph replay when graphs are on, eager launches otherwise)
 double time_product(Ctx& c, int reps) {
   hipStream_t s = c.s_aux;
   const int64_t n = c.rwg.n_e + c.rwg.n_t;
@@ -654,15 +655,20 @@ double time_product(Ctx& c, int reps) {
   hipEvent_t a, b;
   SLIM_HIP(hipEventCreate(&a));
   SLIM_HIP(hipEventCreate(&b));
-  matvec(c, SLIM_MIXED, x.p, y.p, nullptr, nullptr, nullptr, nullptr, s);
+  auto run = [&]() {
+    if (c.opts.use_graphs) matvec_graph(c, SLIM_MIXED, x.p, y.p, s);
+    else matvec(c, SLIM_MIXED, x.p, y.p, nullptr, nullptr, nullptr, nullptr, s);
+  };
+  run();
   SLIM_HIP(hipEventRecord(a, s));
-  for (int r = 0; r < reps; ++r) matvec(c, SLIM_MIXED, x.p, y.p, nullptr, nullptr, nullptr, nullptr, s);
+  for (int r = 0; r < reps; ++r) run();
   SLIM_HIP(hipEventRecord(b, s));
   SLIM_HIP(hipEventSynchronize(b));
   float ms = 0.f;
   SLIM_HIP(hipEventElapsedTime(&ms, a, b));
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(b);
+  c.drop_graphs();   // captured for the temporary vectors freed below
   return double(ms) / reps;
 }
 

@@ -43,3 +43,20 @@ def test_gmres_not_converged_returns_best_iterate(c1_mesh):
     x = torch.zeros_like(b)
     info, ok = ctx.solve(b, x, tol=1e-12, restart=20, max_iter=40, prec=0, scaled_rhs=True, use_precond=False)
     assert not ok and info.iterations == 40 and 0 < info.rel_residual < 1
+
+
+def test_planewave_rhs_matches_oracle(c1_mesh, c1_rwg):
+    """Right-hand side of (7) for a plane wave: tested incident field on the RWG rows,
+    zero on the continuity rows (oracle: planewave_rhs, same TRI(4) rule, which is
+    exact to rounding for this nearly linear integrand)."""
+    import torch
+    from oracle.operators import Physics, planewave_rhs
+    ctx, lay = context(c1_mesh, freq=10e9, grid=(0, 0, 0), precond=0)
+    for khat, epol in (((0.0, 0.0, -1.0), (1.0, 0.0, 0.0)), ((0.6, 0.0, 0.8), (0.0, 1.0, 0.0))):
+        b = torch.zeros(lay.n_sys, dtype=torch.complex128, device='cuda')
+        ctx.rhs_planewave(khat, epol, b)
+        torch.cuda.synchronize()
+        ref = planewave_rhs(c1_rwg, Physics(10e9), khat, epol)
+        got = b.cpu().numpy()
+        assert np.abs(got[lay.n_e:]).max() == 0.0
+        assert np.linalg.norm(got - ref) <= 1e-12 * np.linalg.norm(ref)
