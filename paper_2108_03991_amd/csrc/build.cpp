@@ -144,21 +144,26 @@ template <class T> void up(DevBuf& b, const std::vector<T>& v) { b.upload(v); }
 // The interior EFIE matrices at low frequency have pivots spanning about eight
 // decades; explicit inversion of diagonal blocks (as in rocBLAS TRSM) loses all
 // accuracy on such factors, substitution does not.
-void lu_solve(rocblas_handle h, int n, double* LU, const rocblas_int* ipiv, double* B, hipStream_t s) {
+// B has nrhs columns (leading dimension n).
+void lu_solve_rhs(rocblas_handle h, int n, double* LU, const rocblas_int* ipiv, double* B, int nrhs, hipStream_t s) {
   auto Z = [](double* p) { return reinterpret_cast<rocblas_double_complex*>(p); };
-  SLIM_ROC(rocsolver_zlaswp(h, n, Z(B), n, 1, n, ipiv, 1));
+  SLIM_ROC(rocsolver_zlaswp(h, nrhs, Z(B), n, 1, n, ipiv, 1));
   rocblas_double_complex one{1.0, 0.0}, mone{-1.0, 0.0};
-  SLIM_ROC(rocblas_ztrsm(h, rocblas_side_left, rocblas_fill_lower, rocblas_operation_none, rocblas_diagonal_unit, n, n,
-                         &one, Z(LU), n, Z(B), n));
+  SLIM_ROC(rocblas_ztrsm(h, rocblas_side_left, rocblas_fill_lower, rocblas_operation_none, rocblas_diagonal_unit, n,
+                         nrhs, &one, Z(LU), n, Z(B), n));
   const int nb = 32;
   for (int i1 = n; i1 > 0;) {
     const int i0 = std::max(0, i1 - nb);
-    launch_usolve_block(LU, n, i0, i1 - i0, B, n, n, s);
+    launch_usolve_block(LU, n, i0, i1 - i0, B, n, nrhs, s);
     if (i0 > 0)
-      SLIM_ROC(rocblas_zgemm(h, rocblas_operation_none, rocblas_operation_none, i0, n, i1 - i0, &mone,
+      SLIM_ROC(rocblas_zgemm(h, rocblas_operation_none, rocblas_operation_none, i0, nrhs, i1 - i0, &mone,
                              Z(LU) + int64_t(i0) * n, n, Z(B) + i0, n, &one, Z(B), n));
     i1 = i0;
   }
+}
+
+void lu_solve(rocblas_handle h, int n, double* LU, const rocblas_int* ipiv, double* B, hipStream_t s) {
+  lu_solve_rhs(h, n, LU, ipiv, B, n, s);
 }
 
 Ctx::~Ctx() {

@@ -44,7 +44,7 @@
 namespace slim {
 
 std::vector<int32_t> near_candidates(const RWGTable& r, int64_t t0, int64_t t1, double c_near);   // build.cpp
-void lu_solve(rocblas_handle h, int n, double* LU, const rocblas_int* ipiv, double* B, hipStream_t s);
+void lu_solve_rhs(rocblas_handle h, int n, double* LU, const rocblas_int* ipiv, double* B, int nrhs, hipStream_t s);
 
 namespace {
 
@@ -175,15 +175,18 @@ struct Partitioner {
   }
 };
 
+// column panels of the (I - M) gather and of the block inverse (bounds the build buffers)
+constexpr int64_t kPanel = 2048;
+
 struct Plan {
   std::vector<Part> parts;
   int64_t cap = 0;
   int64_t stored = 0;          // complex64 entries (rows x padded ext)
   int64_t n_ext = 0, n_own = 0;
-  size_t t_la = 0, t_lp = 0, t_mc = 0, t_w = 0, t_b = 0, t_ipiv = 0, t_emap = 0, t_tmap = 0;
+  size_t t_la = 0, t_lp = 0, t_mc = 0, t_w = 0, t_b = 0, t_x = 0, t_ipiv = 0, t_emap = 0, t_tmap = 0;
   size_t bytes() const {
-    return size_t(stored) * 8 + size_t(n_ext) * (8 + 4) + size_t(n_own) * 4 + t_la + t_lp + t_mc + t_w + 2 * t_b + t_ipiv +
-           t_emap + t_tmap + (size_t(1) << 24);
+    return size_t(stored) * 8 + size_t(n_ext) * (8 + 4) + size_t(n_own) * 4 + t_la + t_lp + t_mc + t_w + t_b + t_x +
+           t_ipiv + t_emap + t_tmap + (size_t(1) << 24);
   }
 };
 
@@ -201,9 +204,10 @@ Plan make_plan(Partitioner& P, const RWGTable& r, int64_t cap, int overlap) {
     pl.n_own += int64_t(q.own_pos.size());
     pl.t_la = std::max(pl.t_la, size_t(E * n) * 16);
     pl.t_lp = std::max(pl.t_lp, size_t(q.n_R * t) * 16);
-    pl.t_mc = std::max(pl.t_mc, size_t(n * E) * 16);
+    pl.t_mc = std::max(pl.t_mc, size_t(n * std::min<int64_t>(E, kPanel)) * 16);
     pl.t_w = std::max(pl.t_w, size_t(E * E) * 16);
     pl.t_b = std::max(pl.t_b, size_t(s * s) * 16);
+    pl.t_x = std::max(pl.t_x, size_t(s * std::min<int64_t>(s, kPanel)) * 16);
     pl.t_ipiv = std::max(pl.t_ipiv, size_t(s) * sizeof(rocblas_int));
     pl.t_emap = std::max(pl.t_emap, size_t(n) * 4);
     pl.t_tmap = std::max(pl.t_tmap, size_t(t) * 4);
@@ -219,13 +223,13 @@ __device__ __forceinline__ double2 arena(const float2* hi, const float2* lo, int
   return make_double2(double(h.x) + double(l.x), double(h.y) + double(l.y));
 }
 
-// Mc[k + c n] = delta(k, E[c]) - M_i[k, E[c]]   (n x E, column-major)
-__global__ void k_pc_mcols(const float2* hi, const float2* lo, int64_t off, int n, int ld, const int32_t* Eloc, int E,
-                           double2* Mc) {
+// Mc[k + c n] = delta(k, E[c0 + c]) - M_i[k, E[c0 + c]]  for c < w  (n x w, column-major)
+__global__ void k_pc_mcols(const float2* hi, const float2* lo, int64_t off, int n, int ld, const int32_t* Eloc, int c0,
+                           int w, double2* Mc) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= int64_t(n) * E) return;
+  if (i >= int64_t(n) * w) return;
   const int k = int(i % n), c = int(i / n);
-  const int q = Eloc[c];
+  const int q = Eloc[c0 + c];
   const double2 m = arena(hi, lo, off + int64_t(n + k) * ld + q);
   Mc[i] = make_double2((k == q ? 1.0 : 0.0) - m.x, -m.y);
 }
@@ -373,23 +377,29 @@ __global__ void k_pc_far_grid(FarArgs a) {
   a.L[r + col * a.ld] = make_double2(sr, si);
 }
 
-__global__ void k_pc_eye(double2* X, int64_t s) {
+// columns [c0, c0 + w) of the s x s identity (column-major s x w)
+__global__ void k_pc_eye(double2* X, int64_t s, int64_t c0, int64_t w) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= s * s) return;
-  X[i] = make_double2((i % s) == (i / s) ? 1.0 : 0.0, 0.0);
+  if (i >= s * w) return;
+  X[i] = make_double2((i % s) == c0 + (i / s) ? 1.0 : 0.0, 0.0);
 }
 
-// own rows of the inverse (column-major s x s) -> complex64 row-major, ld >= s
-__global__ void k_pc_pack(const double2* X, int64_t s, const int32_t* own_pos, int n_own, int ld, float2* out) {
+// own rows of columns [c0, c0 + w) of the inverse (column-major s x w panel) ->
+// complex64 rows of length ld >= s; the padding column(s) past s are zeroed by the
+// last panel
+__global__ void k_pc_pack(const double2* X, int64_t s, int64_t c0, int64_t w, const int32_t* own_pos, int n_own, int ld,
+                          float2* out) {
+  const int64_t wp = (c0 + w == s) ? w + (ld - s) : w;   // columns written by this panel
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= int64_t(n_own) * ld) return;
-  const int r = int(i / ld), c = int(i % ld);
+  if (i >= int64_t(n_own) * wp) return;
+  const int r = int(i / wp);
+  const int64_t c = i % wp;
   float2 v = make_float2(0.f, 0.f);
-  if (c < s) {
-    const double2 x = X[own_pos[r] + int64_t(c) * s];
+  if (c < w) {
+    const double2 x = X[own_pos[r] + c * s];
     v = make_float2(float(x.x), float(x.y));
   }
-  out[i] = v;
+  out[int64_t(r) * ld + c0 + c] = v;
 }
 
 // ---------------------------------------------------------------------------
@@ -601,7 +611,7 @@ void build_precond(Ctx& c, hipStream_t s) {
   mc.alloc(std::max<size_t>(16, plan.t_mc));
   w.alloc(std::max<size_t>(16, plan.t_w));
   B.alloc(std::max<size_t>(16, plan.t_b));
-  X.alloc(std::max<size_t>(16, plan.t_b));
+  X.alloc(std::max<size_t>(16, plan.t_x));
   ipiv.alloc(std::max<size_t>(16, plan.t_ipiv));
   info.alloc(sizeof(rocblas_int) * std::max<size_t>(1, plan.parts.size()));
   SLIM_HIP(hipMemsetAsync(info.p, 0, info.bytes, s));
@@ -711,14 +721,15 @@ void build_precond(Ctx& c, hipStream_t s) {
       }
     }
     // W = L_A[E,:] (I - M)[:, E]  (a part may own triangles only)
-    if (E > 0) {
-      hipLaunchKernelGGL(k_pc_mcols, dim3(nb256(int64_t(n) * E)), dim3(256), 0, s, c.d_hi.as<float2>(),
-                         c.d_lo.as<float2>(), ob.off, n, ld, dE.as<int32_t>(), int(E), mc.as<double2>());
+    for (int64_t c0 = 0; c0 < E; c0 += kPanel) {
+      const int64_t wdt = std::min(kPanel, E - c0);
+      hipLaunchKernelGGL(k_pc_mcols, dim3(nb256(int64_t(n) * wdt)), dim3(256), 0, s, c.d_hi.as<float2>(),
+                         c.d_lo.as<float2>(), ob.off, n, ld, dE.as<int32_t>(), int(c0), int(wdt), mc.as<double2>());
       SLIM_HIP(hipGetLastError());
       rocblas_double_complex one{1.0, 0.0}, zero{0.0, 0.0};
-      SLIM_ROCP(rocblas_zgemm(h, rocblas_operation_none, rocblas_operation_none, int(E), int(E), n, &one,
+      SLIM_ROCP(rocblas_zgemm(h, rocblas_operation_none, rocblas_operation_none, int(E), int(wdt), n, &one,
                               la.as<rocblas_double_complex>(), int(E), mc.as<rocblas_double_complex>(), n, &zero,
-                              w.as<rocblas_double_complex>(), int(E)));
+                              w.as<rocblas_double_complex>() + c0 * E, int(E)));
     }
     FillArgs fa{};
     fa.W = w.as<double2>(); fa.E = E;
@@ -744,17 +755,23 @@ void build_precond(Ctx& c, hipStream_t s) {
     // FP64 LU and inverse of the block; keep the owned rows in complex64
     SLIM_ROCP(rocsolver_zgetrf(h, int(S), int(S), B.as<rocblas_double_complex>(), int(S), ipiv.as<rocblas_int>(),
                                info.as<rocblas_int>() + bi));
-    hipLaunchKernelGGL(k_pc_eye, dim3(nb256(S * S)), dim3(256), 0, s, X.as<double2>(), S);
-    SLIM_HIP(hipGetLastError());
-    lu_solve(h, int(S), B.as<double>(), ipiv.as<rocblas_int>(), X.as<double>(), s);
-    hipLaunchKernelGGL(k_pc_colsum, dim3(unsigned(S)), dim3(256), 0, s, X.as<double2>(), S, colsum.as<double>());
-    SLIM_HIP(hipGetLastError());
-    SLIM_HIP(hipMemcpyAsync(cs.data(), colsum.p, size_t(S) * 8, hipMemcpyDeviceToHost, s));
-    SLIM_HIP(hipStreamSynchronize(s));
-    c.pc_cond.push_back(nb1 * *std::max_element(cs.begin(), cs.end()));
-    hipLaunchKernelGGL(k_pc_pack, dim3(nb256(int64_t(pb.n_own) * pb.ld)), dim3(256), 0, s, X.as<double2>(), S,
-                       dpos.as<int32_t>(), pb.n_own, pb.ld, c.d_pc.as<float2>() + pb.off);
-    SLIM_HIP(hipGetLastError());
+    double nx1 = 0.0;
+    for (int64_t c0 = 0; c0 < S; c0 += kPanel) {
+      const int64_t wdt = std::min(kPanel, S - c0);
+      hipLaunchKernelGGL(k_pc_eye, dim3(nb256(S * wdt)), dim3(256), 0, s, X.as<double2>(), S, c0, wdt);
+      SLIM_HIP(hipGetLastError());
+      lu_solve_rhs(h, int(S), B.as<double>(), ipiv.as<rocblas_int>(), X.as<double>(), int(wdt), s);
+      hipLaunchKernelGGL(k_pc_colsum, dim3(unsigned(wdt)), dim3(256), 0, s, X.as<double2>(), S, colsum.as<double>());
+      SLIM_HIP(hipGetLastError());
+      const int64_t wp = (c0 + wdt == S) ? wdt + (pb.ld - S) : wdt;
+      hipLaunchKernelGGL(k_pc_pack, dim3(nb256(int64_t(pb.n_own) * wp)), dim3(256), 0, s, X.as<double2>(), S, c0,
+                         wdt, dpos.as<int32_t>(), pb.n_own, pb.ld, c.d_pc.as<float2>() + pb.off);
+      SLIM_HIP(hipGetLastError());
+      SLIM_HIP(hipMemcpyAsync(cs.data(), colsum.p, size_t(wdt) * 8, hipMemcpyDeviceToHost, s));
+      SLIM_HIP(hipStreamSynchronize(s));
+      nx1 = std::max(nx1, *std::max_element(cs.begin(), cs.begin() + wdt));
+    }
+    c.pc_cond.push_back(nb1 * nx1);
     SLIM_HIP(hipStreamSynchronize(s));   // the index buffers are reused by the next block
     if (o.verbose) {
       static thread_local auto last = std::chrono::steady_clock::now();

@@ -89,11 +89,19 @@ def test_apply_matches_oracle(boxes_oracle, cap, overlap):
         assert err <= 1e-4 * np.linalg.norm(z_ref)
 
 
-def test_single_conductor_inverts_the_system(c1_mesh):
-    """One conductor, dense external operator: P = S A, so P^{-1} S A x = x."""
+@pytest.mark.parametrize("size", ["small", "two_panels"])
+def test_single_conductor_inverts_the_system(size):
+    """One conductor, dense external operator: P = S A, so P^{-1} S A x = x.
+    The second case has more than 2048 unknowns, so its inverse and its (I - M)
+    gather are built in several column panels."""
     import torch
-    m = bar_c1(div=(12, 1, 1), length=30e-6)
+    if size == "small":
+        m = bar_c1(div=(12, 1, 1), length=30e-6)
+    else:
+        m = merge([box_mesh((0.0, 0.0, 0.0), (40e-6, 4e-6, 3e-6), (40, 4, 3))])
     ctx, lay = context(m, freq=10e9, grid=(0, 0, 0))
+    if size != "small":
+        assert lay.n_sys > 2048
     assert lay.precond_blocks == 1
     x = torch.tensor(random_complex(lay.n_sys, 3), device='cuda')
     y = torch.zeros_like(x)

@@ -26,7 +26,7 @@ def big_case():
     grid = aim.make_grid(g.verts, (64, 64, 64))
     cE, wE, cT, wT = aim.stencil_weights(grid, g)
     print("case: 400 conductors, grid 64^3, n_e", g.n_e, flush=True)
-    ctx, lay = context(m, freq=5e9, grid=(64, 64, 64), precond=0)
+    ctx, lay = context(m, freq=5e9, grid=(64, 64, 64))
     return m, g, grid, (cE, wE, cT, wT), ctx, lay
 
 
@@ -57,3 +57,36 @@ def test_near_field_sampled_over_whole_csr(big_case, which):
     scale = np.abs(ref).max()
     err = np.abs(val[z] - ref)
     assert err.max() <= 1e-9 * scale, (err.max() / scale, int(z[np.argmax(err)]))
+
+
+def test_conductor_blocks_invert_the_operators_self_part(big_case):
+    """A property that holds at any size: for x supported on one conductor, the rows
+    of S A x on that conductor are that conductor's block times x. So applying the
+    block inverse gives back x, up to the complex64 storage of the inverse.
+
+    This checks the operator and the preconditioner against each other, and it
+    fails if either drops part of a conductor's self interaction (the near field,
+    the grid part or the internal blocks)."""
+    import torch
+    from inputs.geometry import random_complex
+    m, g, grid, _, ctx, lay = big_case
+    assert lay.precond_blocks > 0
+    n = lay.n_sys
+    h = lay.mean_edge
+    s = torch.cat([torch.full((lay.n_e,), 1.0 / h ** 2, dtype=torch.float64),
+                   torch.full((lay.n_t,), h, dtype=torch.float64)]).cuda()
+    blocks = ctx.get_precond()
+    whole = [b for b in blocks if len(b[1]) == len(b[0])]
+    rng = np.random.default_rng(2)
+    for k in rng.choice(len(whole), 6, replace=False):
+        ext = whole[k][0]
+        idx = torch.tensor(ext, device='cuda')
+        x = torch.zeros(n, dtype=torch.complex128, device='cuda')
+        x[idx] = torch.tensor(random_complex(len(ext), int(k)), device='cuda')
+        y = torch.zeros_like(x)
+        ctx.matvec(0, x, y)
+        z = torch.zeros_like(x)
+        ctx.precond_apply(y * s, z)
+        torch.cuda.synchronize()
+        err = float(torch.linalg.norm((z - x)[idx]) / torch.linalg.norm(x))
+        assert err <= 1e-2, (int(k), len(ext), err)
