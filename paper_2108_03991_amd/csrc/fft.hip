@@ -132,6 +132,16 @@ struct PassArgs {
   int64_t comp_in, comp_out;   // component strides (blockIdx.z)
 };
 
+// Streaming accesses: every element of a pass is read once and written once, and
+// the arrays (1-2 GB) are far larger than the caches.
+template <class T> __device__ __forceinline__ C2<T> ld_stream(const C2<T>* p) {
+  return {__builtin_nontemporal_load(&p->x), __builtin_nontemporal_load(&p->y)};
+}
+template <class T> __device__ __forceinline__ void st_stream(C2<T>* p, C2<T> v) {
+  __builtin_nontemporal_store(v.x, &p->x);
+  __builtin_nontemporal_store(v.y, &p->y);
+}
+
 // MODE 0: forward, 1: inverse, 2: forward, multiply, inverse.
 // CONTIG: lines are contiguous (in_e == 1), batch = consecutive lines along o1;
 // otherwise the batch is W = ELEMS/L adjacent lines (o1 stride 1) for coalescing.
@@ -163,7 +173,7 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_pass(PassArgs a) {
     if (CONTIG) { b = e / L; i = e % L; } else { b = e % W; i = e / W; }
     const int o1 = g1 + b;
     C2<T> v = {T(0), T(0)};
-    if (o1 < a.n1 && i < a.n_in) v = in[o1 * a.in_o1 + o2 * a.in_o2 + int64_t(i) * a.in_e];
+    if (o1 < a.n1 && i < a.n_in) v = ld_stream(in + (o1 * a.in_o1 + o2 * a.in_o2 + int64_t(i) * a.in_e));
     lds[pidx<L>(b, i)] = v;
   }
   __syncthreads();
@@ -186,7 +196,7 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_pass(PassArgs a) {
     int b, i;
     if (CONTIG) { b = e / L; i = e % L; } else { b = e % W; i = e / W; }
     const int o1 = g1 + b;
-    if (o1 < a.n1 && i < a.n_out) out[o1 * a.out_o1 + o2 * a.out_o2 + int64_t(i) * a.out_e] = lds[pidx<L>(b, i)];
+    if (o1 < a.n1 && i < a.n_out) st_stream(out + (o1 * a.out_o1 + o2 * a.out_o2 + int64_t(i) * a.out_e), lds[pidx<L>(b, i)]);
   }
 }
 
