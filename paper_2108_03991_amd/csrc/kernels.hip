@@ -323,10 +323,14 @@ __global__ void __launch_bounds__(256) k_phi(const int32_t* wt_base, const void*
     sr = wv * Phi[node].x;
     si = wv * Phi[node].y;
   }
-  for (int64_t z = ptr[t] + lane; z < ptr[t + 1]; z += 64) {
-    const C2<T> a = val[z], b = rho[col[z]];
-    sr += a.x * b.x - a.y * b.y;
-    si += a.x * b.y + a.y * b.x;
+  const int64_t zend = ptr[t + 1];
+  for (int64_t z = ptr[t] + lane; z < zend; z += 128) {
+    const bool two = z + 64 < zend;
+    const int c0 = col[z], c1 = two ? col[z + 64] : c0;
+    const C2<T> a0 = val[z], a1 = two ? val[z + 64] : C2<T>{T(0), T(0)};
+    const C2<T> b0 = rho[c0], b1 = rho[c1];
+    sr += a0.x * b0.x - a0.y * b0.y + a1.x * b1.x - a1.y * b1.y;
+    si += a0.x * b0.y + a0.y * b0.x + a1.x * b1.y + a1.y * b1.x;
   }
   sr = wave_sum(sr);
   si = wave_sum(si);
@@ -364,10 +368,15 @@ __global__ void __launch_bounds__(256) k_rows_A(const int32_t* we_base, const vo
     }
     const C2<T>* val = reinterpret_cast<const C2<T>*>(valv);
     const C2<T>* j = reinterpret_cast<const C2<T>*>(jv);
-    for (int64_t z = ptr[m] + lane; z < ptr[m + 1]; z += 64) {
-      const C2<T> a = val[z], b = j[col[z]];
-      sr += a.x * b.x - a.y * b.y;
-      si += a.x * b.y + a.y * b.x;
+    // two entries per lane per trip: both column loads, then both gathers, are in flight together
+    const int64_t zend = ptr[m + 1];
+    for (int64_t z = ptr[m] + lane; z < zend; z += 128) {
+      const bool two = z + 64 < zend;
+      const int c0 = col[z], c1 = two ? col[z + 64] : c0;
+      const C2<T> a0 = val[z], a1 = two ? val[z + 64] : C2<T>{T(0), T(0)};
+      const C2<T> b0 = j[c0], b1 = j[c1];
+      sr += a0.x * b0.x - a0.y * b0.y + a1.x * b1.x - a1.y * b1.y;
+      si += a0.x * b0.y + a0.y * b0.x + a1.x * b1.y + a1.y * b1.x;
     }
     sr = wave_sum(sr);
     si = wave_sum(si);
