@@ -16,6 +16,7 @@ function names the passage it follows.  Modules:
     aim        AIM decomposition (11): stencils P, grid convolution H, W = P^T,
                precorrected near field L_NR
     solve      dense LU solve, FP64 GMRES and flexible GMRES of (7)
+    mgf        reflected multilayered-medium Green's functions (Sommerfeld integrals, TL model)
     precond    conductor-block (block Jacobi / restricted additive Schwarz) preconditioner
     sched      LPT (Alg. 1, bound (13)), modified Part_Schedule (Alg. 2, (14))
     mlp        FP64 reference of the scheduler's cost-model network
