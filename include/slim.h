@@ -204,6 +204,63 @@ slim_status slim_internal_apply(slim_ctx* ctx, slim_prec prec, const void* H_dev
 slim_status slim_aim_convolve(slim_ctx* ctx, slim_prec prec, const void* src_dev, void* dst_dev, int32_t ncomp,
                               void* stream);
 slim_status slim_get_aim(const slim_ctx* ctx, int32_t* cidx_e, double* w_e, int32_t* cidx_t, double* w_t);
+
+/* --- layered background medium (Sec. II: L_A,m and L_phi,m with the multilayered
+ * Green's function; the substrates of Table I) --------------------------------
+ * The conductors and every AIM grid node lie in air above the plane
+ * z = z_interface.  Below it, n_layers layers are listed top-down; the stack
+ * ends in a PEC ground (bottom_pec = 1) or in a half-space (bottom_eps_r,
+ * bottom_sigma).  Conductivities are in S/m and thicknesses in metres. */
+typedef struct slim_layer {
+  double thickness;
+  double eps_r;
+  double sigma;
+} slim_layer;
+
+typedef struct slim_medium {
+  double z_interface;
+  int32_t n_layers;
+  int32_t bottom_pec;
+  const slim_layer* layers;   /* host array of n_layers entries, copied */
+  double bottom_eps_r;
+  double bottom_sigma;
+} slim_medium;
+
+/* slim_set_medium: builds the reflected grid kernels of the built AIM grid at
+ * the build frequency.  Their spectra are then used by
+ * slim_aim_convolve_layered.
+ *   Each kernel is a Sommerfeld integral of the stack's TL reflection
+ *   coefficients, in FP64.  It is evaluated on the device at every in-plane
+ *   lattice offset and every z + z' lattice sum.
+ *   The kernels: the xx = yy entry, the zz entry and the scalar kernel, all
+ *   even; and the radial factor of zx, so that G_zx = (x - x')/rho times it,
+ *   G_zy = (y - y')/rho times it, and G_xz = -G_zx, G_yz = -G_zy.
+ *   Normalised by mu0 and 1/eps0, like the free-space g = e^{-jk0R}/(4 pi R).
+ * Errors:
+ *   SLIM_E_STATE: no AIM operator built.
+ *   SLIM_E_ARG: bad layer data, or the grid reaches the interface.
+ *   SLIM_E_UNSUPPORTED: the grid is too large electrically for the
+ *   quadrature path.
+ * Replaces any earlier medium.
+ *
+ * slim_aim_convolve_layered: the four grid components (x, y, z current and
+ *   charge; 4 x Nx Ny Nz complex128 device arrays, node order x fastest),
+ *   convolved with the free-space kernel plus the reflected dyadic.  The
+ *   reflected part is a convolution in x and y and a correlation in z:
+ *     Phi_x = (g + xx) * S_x + G_xz * S_z,
+ *     Phi_y = (g + xx) * S_y + G_yz * S_z,
+ *     Phi_z = G_zx * S_x + G_zy * S_y + (g + zz) * S_z,
+ *     Phi_rho = (g + phi) * S_rho.
+ *   SLIM_E_STATE without a medium.
+ *
+ * slim_get_layered_kernels: host copy of the four reflected kernels on the
+ *   lattice, [4][2 Nz - 1][Ny][Nx] complex128 in the order xx, zz, phi, zx.
+ *   Index s of the second axis is z + z' - 2 z_interface =
+ *   2 (origin_z - z_interface) + s h_z; the last two axes are |offset| in
+ *   nodes. */
+slim_status slim_set_medium(slim_ctx* ctx, const slim_medium* medium);
+slim_status slim_aim_convolve_layered(slim_ctx* ctx, slim_prec prec, const void* src_dev, void* dst_dev, void* stream);
+slim_status slim_get_layered_kernels(const slim_ctx* ctx, double* out);
 slim_status slim_get_near(const slim_ctx* ctx, int32_t which, int64_t* ptr, int32_t* col, double* val);
 
 /* Right-hand side of (7) for an incident plane wave E0 epol e^{-j k0 khat.r}. */

@@ -342,6 +342,47 @@ slim_status slim_aim_convolve(slim_ctx* h, slim_prec prec, const void* src, void
   });
 }
 
+slim_status slim_set_medium(slim_ctx* h, const slim_medium* m) {
+  return guard(h, [&]() {
+    SLIM_REQUIRE(m, SLIM_E_ARG, "null medium");
+    SLIM_HIP(hipSetDevice(h->c.device));
+    h->c.layered = false;
+    build_layered(h->c, *m, h->c.s_aux);
+    return SLIM_OK;
+  });
+}
+
+slim_status slim_aim_convolve_layered(slim_ctx* h, slim_prec prec, const void* src, void* dst, void* stream) {
+  return guard(h, [&]() {
+    SLIM_REQUIRE(h->c.built && !h->c.plain, SLIM_E_STATE, "no AIM operator built");
+    SLIM_REQUIRE(h->c.layered, SLIM_E_STATE, "no layered medium set");
+    SLIM_REQUIRE(src && dst, SLIM_E_ARG, "bad arguments");
+    SLIM_HIP(hipSetDevice(h->c.device));
+    hipStream_t s = as_stream(stream);
+    const int64_t n = 4 * h->c.grid.nodes();
+    const bool f64 = prec == SLIM_FP64;
+    void* in = f64 ? h->c.d_oct_in.p : h->c.d_oct_in32.p;
+    if (f64) SLIM_HIP(hipMemcpyAsync(in, src, size_t(n) * 16, hipMemcpyDeviceToDevice, s));
+    else launch_cast_c128_to_c64(src, in, n, s);
+    aim_convolve_layered(h->c, f64, s);
+    if (f64) SLIM_HIP(hipMemcpyAsync(dst, h->c.d_oct_out.p, size_t(n) * 16, hipMemcpyDeviceToDevice, s));
+    else launch_cast_c64_to_c128(h->c.d_oct_out.p, dst, n, s);
+    // the projection buffers must stay zero off the occupied nodes
+    SLIM_HIP(hipMemsetAsync(in, 0, size_t(n) * (f64 ? 16 : 8), s));
+    SLIM_HIP(hipStreamSynchronize(s));
+    return SLIM_OK;
+  });
+}
+
+slim_status slim_get_layered_kernels(const slim_ctx* h, double* out) {
+  if (!h) return SLIM_E_ARG;
+  if (!h->c.layered) return SLIM_E_STATE;
+  if (!out) return SLIM_E_ARG;
+  if (hipSetDevice(h->c.device) != hipSuccess) return SLIM_E_HIP;
+  if (hipMemcpy(out, h->c.d_lay_real.p, h->c.d_lay_real.bytes, hipMemcpyDeviceToHost) != hipSuccess) return SLIM_E_HIP;
+  return SLIM_OK;
+}
+
 slim_status slim_get_aim(const slim_ctx* h, int32_t* ce, double* we, int32_t* ct, double* wt) {
   if (!h) return SLIM_E_ARG;
   if (!h->c.built || h->c.plain) return SLIM_E_STATE;

@@ -95,6 +95,13 @@ struct Ctx {
   // FFT work arrays (4 components)
   DevBuf d_oct_in, d_oct_in32;          // projected sources: complex128 / complex64 (zero off the occupied nodes)
   DevBuf d_oct_out, d_x1, d_x2;         // sized for complex128; complex64 uses the front
+  // layered background: reflected kernels on the lattice [4][2Nz-1][Ny][Nx] (xx, zz, phi, zx radial),
+  // their spectra [5][2Nz][Ny+1][Nx+1] (xx, zz, phi, zx, zy; scaled by 1/(2N)^3) and the
+  // full-z work array of the layered z step (4 components, sized for complex128)
+  bool layered = false;
+  double lay_zif = 0.0;
+  int lay_nodes = 0;
+  DevBuf d_lay_real, d_rhat128, d_rhat64, d_lay;
   std::vector<int32_t> h_cidx_e, h_cidx_t;     // stencil centres (host copies)
   std::vector<double> h_w_e, h_w_t;            // stencil weights (host copies)
   // near field
@@ -161,6 +168,9 @@ void launch_pack_dense(const double* Acm, int64_t rows, int64_t cols, Cplx<float
 void fft_init_twiddles(Ctx& c);
 void fft_forward_3d_c128(Ctx& c, double* data_full, hipStream_t s);   // full (2N)^3 in place (build)
 void aim_convolve(Ctx& c, bool fp64, int ncomp, hipStream_t s, int comp0 = 0);   // oct_in -> oct_out
+void aim_convolve_layered(Ctx& c, bool fp64, hipStream_t s);   // oct_in -> oct_out, 4 components
+// layered.hip
+void build_layered(Ctx& c, const slim_medium& m, hipStream_t s);
 // sched.cpp
 void pack_tiles(Ctx& c, int mode);
 // precond.hip

@@ -226,6 +226,53 @@ void launch_pass_L(int L, const PassArgs& a, int ncomp, hipStream_t s) {
   SLIM_HIP(hipGetLastError());
 }
 
+// Spectrum product of the layered medium on the full-z spectra of the four
+// components (lay: [comp][Z2][Y2][X2]), in place.  The reflected kernels depend on
+// z + z', so they multiply the source spectrum at -kz; each thread takes the pair
+// (kz, Z2 - kz) and writes both.  G^ (free space) is the even octant; the reflected
+// spectra cover kx <= Nx, ky <= Ny (mirrored; zx odd in x, zy odd in y) and all kz.
+template <class T>
+__global__ void k_layered_mix(C2<T>* S, int64_t comp, const C2<T>* gp, const C2<T>* rh, int64_t spec, int Nx, int Ny,
+                              int Nz) {
+  const int X2 = 2 * Nx, Y2 = 2 * Ny, Z2 = 2 * Nz;
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t plane = int64_t(X2) * Y2;
+  if (i >= plane * (Nz + 1)) return;
+  const int kx = int(i % X2), ky = int((i / X2) % Y2), k1 = int(i / plane);
+  const int k2 = (Z2 - k1) % Z2;
+  const int mx = kx <= Nx ? kx : X2 - kx, my = ky <= Ny ? ky : Y2 - ky;
+  const T sx = kx <= Nx ? T(1) : T(-1), sy = ky <= Ny ? T(1) : T(-1);
+  const int64_t o1 = int64_t(k1) * plane + int64_t(ky) * X2 + kx, o2 = int64_t(k2) * plane + int64_t(ky) * X2 + kx;
+  C2<T> a[4], b[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    a[c] = S[c * comp + o1];
+    b[c] = S[c * comp + o2];
+  }
+  auto product = [&](int kz, const C2<T>* self, const C2<T>* part, C2<T>* r) {
+    const int mz = kz <= Nz ? kz : Z2 - kz;
+    const C2<T> g = gp[(int64_t(mz) * (Ny + 1) + my) * (Nx + 1) + mx];
+    const int64_t ro = (int64_t(kz) * (Ny + 1) + my) * (Nx + 1) + mx;
+    const C2<T> xx = rh[ro], zz = rh[spec + ro], ph = rh[2 * spec + ro];
+    C2<T> zx = rh[3 * spec + ro], zy = rh[4 * spec + ro];
+    zx = {sx * zx.x, sx * zx.y};
+    zy = {sy * zy.x, sy * zy.y};
+    // G_xz = -G_zx, G_yz = -G_zy
+    r[0] = csub(cadd(cmul(g, self[0]), cmul(xx, part[0])), cmul(zx, part[2]));
+    r[1] = csub(cadd(cmul(g, self[1]), cmul(xx, part[1])), cmul(zy, part[2]));
+    r[2] = cadd(cadd(cmul(g, self[2]), cmul(zz, part[2])), cadd(cmul(zx, part[0]), cmul(zy, part[1])));
+    r[3] = cadd(cmul(g, self[3]), cmul(ph, part[3]));
+  };
+  C2<T> r1[4], r2[4];
+  product(k1, a, b, r1);
+  product(k2, b, a, r2);
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    S[c * comp + o1] = r1[c];
+    S[c * comp + o2] = r2[c];
+  }
+}
+
 }  // namespace
 
 void fft_init_twiddles(Ctx& c) {
@@ -277,7 +324,7 @@ void fft_forward_3d_c128(Ctx& c, double* data, hipStream_t s) {
 // convolved with the grid Green's function.  Distinct components use disjoint
 // parts of every work array, so two calls on different components may run
 // concurrently.
-void aim_convolve(Ctx& c, bool fp64, int ncomp, hipStream_t s, int comp0) {
+static void convolve_impl(Ctx& c, bool fp64, int ncomp, hipStream_t s, int comp0, bool layered) {
   const int Nx = c.grid.N[0], Ny = c.grid.N[1], Nz = c.grid.N[2];
   const int X2 = 2 * Nx, Y2 = 2 * Ny, Z2 = 2 * Nz;
   const int64_t N3 = c.grid.nodes();
@@ -307,17 +354,44 @@ void aim_convolve(Ctx& c, bool fp64, int ncomp, hipStream_t s, int comp0) {
     a.comp_in = 2 * N3; a.comp_out = 4 * N3;
     a.tw = tw + tw_off(c, 1);
     launch_pass_L<T, false, 0>(Y2, a, ncomp, s);
-    // z fused: X2 lines (kx, ky), stride X2 Y2; forward, x G^, inverse, keep z < Nz
-    a = PassArgs{};
-    a.in = x2; a.out = x2;
-    a.in_e = a.out_e = int64_t(X2) * Y2; a.in_o1 = a.out_o1 = 1; a.in_o2 = a.out_o2 = X2;
-    a.n1 = X2; a.n2 = Y2; a.n_in = Nz; a.n_out = Nz;
-    a.mul = fp64 ? c.d_ghat128.p : c.d_ghat64.p;
-    a.mul_e = int64_t(Nx + 1) * (Ny + 1); a.mul_o1 = 1; a.mul_o2 = Nx + 1;
-    a.h_e = Nz; a.h_o1 = Nx; a.h_o2 = Ny;
-    a.comp_in = a.comp_out = 4 * N3;
-    a.tw = tw + tw_off(c, 2);
-    launch_pass_L<T, false, 2>(Z2, a, ncomp, s);
+    if (!layered) {
+      // z fused: X2 lines (kx, ky), stride X2 Y2; forward, x G^, inverse, keep z < Nz
+      a = PassArgs{};
+      a.in = x2; a.out = x2;
+      a.in_e = a.out_e = int64_t(X2) * Y2; a.in_o1 = a.out_o1 = 1; a.in_o2 = a.out_o2 = X2;
+      a.n1 = X2; a.n2 = Y2; a.n_in = Nz; a.n_out = Nz;
+      a.mul = fp64 ? c.d_ghat128.p : c.d_ghat64.p;
+      a.mul_e = int64_t(Nx + 1) * (Ny + 1); a.mul_o1 = 1; a.mul_o2 = Nx + 1;
+      a.h_e = Nz; a.h_o1 = Nx; a.h_o2 = Ny;
+      a.comp_in = a.comp_out = 4 * N3;
+      a.tw = tw + tw_off(c, 2);
+      launch_pass_L<T, false, 2>(Z2, a, ncomp, s);
+    } else {
+      // layered z step: forward into the full-z work array, spectrum product with
+      // the partner -kz, inverse back (keep z < Nz)
+      char* lay = reinterpret_cast<char*>(c.d_lay.p);
+      a = PassArgs{};
+      a.in = x2; a.out = lay;
+      a.in_e = a.out_e = int64_t(X2) * Y2; a.in_o1 = a.out_o1 = 1; a.in_o2 = a.out_o2 = X2;
+      a.n1 = X2; a.n2 = Y2; a.n_in = Nz; a.n_out = Z2;
+      a.comp_in = 4 * N3; a.comp_out = 8 * N3;
+      a.tw = tw + tw_off(c, 2);
+      launch_pass_L<T, false, 0>(Z2, a, ncomp, s);
+      const int64_t pairs = int64_t(X2) * Y2 * (Nz + 1);
+      const int64_t spec = int64_t(Nx + 1) * (Ny + 1) * Z2;
+      hipLaunchKernelGGL((k_layered_mix<T>), dim3(unsigned((pairs + 255) / 256)), dim3(256), 0, s,
+                         reinterpret_cast<C2<T>*>(lay), 8 * N3,
+                         reinterpret_cast<const C2<T>*>(fp64 ? c.d_ghat128.p : c.d_ghat64.p),
+                         reinterpret_cast<const C2<T>*>(fp64 ? c.d_rhat128.p : c.d_rhat64.p), spec, Nx, Ny, Nz);
+      SLIM_HIP(hipGetLastError());
+      a = PassArgs{};
+      a.in = lay; a.out = x2;
+      a.in_e = a.out_e = int64_t(X2) * Y2; a.in_o1 = a.out_o1 = 1; a.in_o2 = a.out_o2 = X2;
+      a.n1 = X2; a.n2 = Y2; a.n_in = Z2; a.n_out = Nz;
+      a.comp_in = 8 * N3; a.comp_out = 4 * N3;
+      a.tw = tw + tw_off(c, 2);
+      launch_pass_L<T, false, 1>(Z2, a, ncomp, s);
+    }
     // y-inv: X2 [Nz][Y2][X2] -> X1 [Nz][Ny][X2] (keep y < Ny)
     a = PassArgs{};
     a.in = x2; a.out = x1;
@@ -339,6 +413,17 @@ void aim_convolve(Ctx& c, bool fp64, int ncomp, hipStream_t s, int comp0) {
   };
   if (fp64) run(double{});
   else run(float{});
+}
+
+void aim_convolve(Ctx& c, bool fp64, int ncomp, hipStream_t s, int comp0) {
+  convolve_impl(c, fp64, ncomp, s, comp0, false);
+}
+
+// The four components over a layered background (free-space kernel plus the
+// reflected dyadic); needs build_layered.
+void aim_convolve_layered(Ctx& c, bool fp64, hipStream_t s) {
+  SLIM_REQUIRE(c.layered, SLIM_E_STATE, "no layered medium set");
+  convolve_impl(c, fp64, 4, s, 0, true);
 }
 
 }  // namespace slim

@@ -60,6 +60,15 @@ class Material(C.Structure):
     _fields_ = [("sigma", C.c_double), ("eps_r", C.c_double), ("mu_r", C.c_double)]
 
 
+class Layer(C.Structure):
+    _fields_ = [("thickness", C.c_double), ("eps_r", C.c_double), ("sigma", C.c_double)]
+
+
+class Medium(C.Structure):
+    _fields_ = [("z_interface", C.c_double), ("n_layers", C.c_int32), ("bottom_pec", C.c_int32),
+                ("layers", C.POINTER(Layer)), ("bottom_eps_r", C.c_double), ("bottom_sigma", C.c_double)]
+
+
 _lib = None
 
 
@@ -106,6 +115,9 @@ def lib():
         L.slim_precond_apply.argtypes = [vp, vp, vp, vp]
         L.slim_get_precond.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
         L.slim_precond_partition.argtypes = [vp, i64, vp, i64, vp, i32, i64, i32, vp, vp, vp, vp, vp, vp, vp]
+        L.slim_set_medium.argtypes = [vp, C.POINTER(Medium)]
+        L.slim_aim_convolve_layered.argtypes = [vp, i32, vp, vp, vp]
+        L.slim_get_layered_kernels.argtypes = [vp, dp]
         L.slim_profile.argtypes = [vp, i32]
         L.slim_profile_read.argtypes = [vp, dp, C.POINTER(i64)]
         for name in ("slim_create", "slim_set_mesh", "slim_set_materials", "slim_build", "slim_get_layout",
@@ -113,7 +125,8 @@ def lib():
                      "slim_rhs_planewave", "slim_solve", "slim_sched_record", "slim_sched_tiles",
                      "slim_sched_train", "slim_sched_set_mode", "slim_mlp_forward_backward", "slim_profile",
                      "slim_profile_read", "slim_aim_convolve", "slim_get_aim", "slim_get_near",
-                     "slim_precond_apply", "slim_get_precond", "slim_precond_partition"):
+                     "slim_precond_apply", "slim_get_precond", "slim_precond_partition", "slim_set_medium",
+                     "slim_aim_convolve_layered", "slim_get_layered_kernels"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -124,7 +137,8 @@ EXPORTS = ["slim_default_build_opts", "slim_create", "slim_destroy", "slim_last_
            "slim_matvec_parts", "slim_internal_apply", "slim_rhs_planewave", "slim_solve", "slim_sched_record",
            "slim_sched_tiles", "slim_sched_train", "slim_sched_set_mode", "slim_mlp_forward_backward",
            "slim_profile", "slim_profile_read", "slim_aim_convolve", "slim_get_aim", "slim_get_near",
-           "slim_precond_apply", "slim_get_precond", "slim_precond_partition"]
+           "slim_precond_apply", "slim_get_precond", "slim_precond_partition", "slim_set_medium",
+           "slim_aim_convolve_layered", "slim_get_layered_kernels"]
 
 
 def _ptr(t):
@@ -250,6 +264,32 @@ class Context:
 
     def aim_convolve(self, prec, src, dst, ncomp, stream=None):
         self._check(lib().slim_aim_convolve(self._h, prec, _ptr(src), _ptr(dst), int(ncomp), _stream(stream)))
+
+    def set_medium(self, z_interface, layers=(), bottom="pec"):
+        """Layered background: layers top-down as (thickness, eps_r, sigma); bottom "pec" or (eps_r, sigma)."""
+        arr = (Layer * max(1, len(layers)))(*[Layer(*map(float, l)) for l in layers])
+        m = Medium()
+        m.z_interface = float(z_interface)
+        m.n_layers = len(layers)
+        m.layers = C.cast(arr, C.POINTER(Layer))
+        if isinstance(bottom, str):
+            if bottom != "pec":
+                raise ValueError("bottom must be 'pec' or (eps_r, sigma)")
+            m.bottom_pec = 1
+        else:
+            m.bottom_pec = 0
+            m.bottom_eps_r, m.bottom_sigma = (float(v) for v in bottom)
+        self._check(lib().slim_set_medium(self._h, C.byref(m)))
+
+    def aim_convolve_layered(self, prec, src, dst, stream=None):
+        self._check(lib().slim_aim_convolve_layered(self._h, prec, _ptr(src), _ptr(dst), _stream(stream)))
+
+    def layered_kernels(self, grid):
+        """Reflected kernels on the lattice: (4, 2 Nz - 1, Ny, Nx) complex (xx, zz, phi, zx radial)."""
+        Nx, Ny, Nz = (int(v) for v in grid)
+        out = np.zeros(2 * 4 * (2 * Nz - 1) * Ny * Nx)
+        self._check(lib().slim_get_layered_kernels(self._h, out.ctypes.data_as(C.POINTER(C.c_double))))
+        return out.view(np.complex128).reshape(4, 2 * Nz - 1, Ny, Nx)
 
     def get_aim(self, n_e, n_t):
         ce = np.zeros(3 * n_e, np.int32)
