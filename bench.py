@@ -43,7 +43,7 @@ def make_mesh(name, kw):
 
 
 def algorithmic_bytes(mesh, lay, mixed):
-    """Bytes the method must move per product (unit figures: the design doc, measurement)."""
+    """Bytes the method must move per product: every stored operator entry and grid element once."""
     n = np.bincount(mesh.obj)  # triangles per object
     ne_i = (1.5 * n).astype(np.float64)
     sc = 8.0 if mixed else 16.0          # complex element (hi, or hi + lo / complex128)
@@ -208,6 +208,70 @@ def solve_study(ctx, lay, max_iter):
     return out
 
 
+def layered_bytes(N, mixed):
+    """Algorithmic bytes of one layered convolution of four components.
+
+    Per component, the passes move N^3 elements in x-fwd and x-inv (plus 2 N^3
+    each), 6 N^3 in y-fwd and y-inv each, 12 N^3 in the z forward and inverse
+    steps each, and 16 N^3 in the spectrum product (read and write of the full
+    (2N)^2 x 2N spectrum).  Together with the kernels (the free-space octant and
+    five reflected spectra of (N+1)^2 x 2N) that is 58 N^3 elements per component.
+    """
+    N3 = float(N[0] * N[1] * N[2])
+    sc = 8.0 if mixed else 16.0
+    kern = (N[0] + 1) * (N[1] + 1) * (N[2] + 1) + 5 * (N[0] + 1) * (N[1] + 1) * 2 * N[2]
+    return (4 * 58 * N3 + kern) * sc
+
+
+def layered_study(steps=10, warmup=2):
+    """The layered-medium grid convolution on the bundle-over-substrate workload.
+
+    The 200-line bundle (1 GHz, AIM grid 128^3) sits above a silicon substrate
+    (200 um, eps_r 11.9, sigma 10 S/m) on a PEC ground.  The interface is 1 um
+    below the lowest grid plane.  The reflected kernels are built once, then the
+    four-component convolution (free space + reflected) is timed per entry-point
+    call, against the free-space convolution of the same four components.
+    """
+    import torch
+    from paper_2108_03991_amd import slim
+    from inputs.geometry import random_complex
+    kw, freq, grid = WORKLOADS["line_bundle"]
+    mesh = make_mesh("line_bundle", kw)
+    ctx = slim.Context(0)
+    ctx.set_mesh(mesh.verts, mesh.tris, mesh.obj, mesh.n_obj)
+    lay = ctx.build(freq=freq, grid=grid, precond=0)
+    z_if = lay.grid_origin[2] - 1e-6
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.set_medium(z_if, [(200e-6, 11.9, 10.0)], "pec")
+    t_kern = time.perf_counter() - t0
+    n3 = grid[0] * grid[1] * grid[2]
+    src = torch.tensor(random_complex(4 * n3, 5), dtype=torch.complex128, device="cuda")
+    dst = torch.zeros_like(src)
+    out = {"workload": "line_bundle over silicon (200 um, eps_r 11.9, 10 S/m) on PEC", "aim_grid": list(grid),
+           "freq_hz": freq, "z_interface_below_grid_m": 1e-6, "kernel_build_s": t_kern}
+    for name, prec in (("mixed", slim.SLIM_MIXED), ("fp64", slim.SLIM_FP64)):
+        res = {}
+        for kind, call in (("layered", lambda: ctx.aim_convolve_layered(prec, src, dst)),
+                           ("free_space", lambda: ctx.aim_convolve(prec, src, dst, 4))):
+            for _ in range(warmup):
+                call()
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for _ in range(steps):
+                call()
+            torch.cuda.synchronize()
+            res[kind + "_ms"] = 1e3 * (time.perf_counter() - t) / steps
+        b = layered_bytes(grid, prec == slim.SLIM_MIXED)
+        res["layered_algorithmic_bytes"] = b
+        res["layered_hbm_frac"] = b / (res["layered_ms"] * 1e-3) / HBM_PEAK
+        out[name] = res
+    log("layered convolution study: %s" % out)
+    ctx.close()
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -223,6 +287,10 @@ def main():
                     help="only run a plain device copy of this many GiB (HBM counter calibration) and exit")
     ap.add_argument("--no-sched-study", action="store_true",
                     help="skip the makespan study (naive / LPT / trained cost model)")
+    ap.add_argument("--no-layered", action="store_true",
+                    help="skip the layered-medium convolution study (bundle over a silicon substrate)")
+    ap.add_argument("--layered-only", action="store_true",
+                    help="only run the layered-medium convolution study and print its JSON")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the product is built and applied on a single MI355X "
@@ -241,6 +309,9 @@ def main():
     from paper_2108_03991_amd import slim
     from inputs.geometry import random_complex
 
+    if args.layered_only:
+        print(json.dumps({"layered_convolution": layered_study(args.steps, args.warmup)}), flush=True)
+        return
     kw, freq, grid = WORKLOADS[args.workload]
     t0 = time.time()
     mesh = make_mesh(args.workload, kw)
@@ -341,6 +412,10 @@ def main():
         # the second half of the metric: seconds to a 1e-6 FP64 relative residual (null if not reached)
         result["gmres_time_to_1e-6_s"] = {
             k: (result["solve"][k]["seconds"] if result["solve"][k]["converged"] else None) for k in ("mixed", "fp64")}
+    if not args.no_layered:
+        ctx.close()       # frees the device arenas of this workload first
+        torch.cuda.empty_cache()
+        result["layered_convolution"] = layered_study()
     if not args.no_cpu_baseline:
         t0 = time.time()
         result["cpu_baseline"] = cpu_baseline(mesh, lay, freq, grid)
