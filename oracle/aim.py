@@ -314,3 +314,151 @@ def convolve_layered_direct(grid: Grid, freq, stack, src):
     out[2] = (cx * zxr) @ Sx + (cy * zxr) @ Sy + (Gp + zz) @ Sz
     out[3] = (Gp + ph) @ Sr
     return out
+
+
+# ---- layered background: reflected near-field entries and their grid part ----
+# Readings (the reflected kernel is smooth at the triangle scale, since every point
+# lies above the interface): the reflected parts of the near entries are integrated
+# with TRI(2) on both triangles; the precorrection subtracts the reflected dyadic's
+# grid part as well, so that L_NR = L_exact - W G_total P on near pairs.
+
+REFL_ORDER = 2
+
+
+def _tri_rule(g: RWG, order=REFL_ORDER):
+    Vt = g.verts[g.tris]
+    return tri_points(Vt, order)          # (N_T, q, 3), (N_T, q) with weights summing to A_t
+
+
+def _reflected_pair_integrals(g: RWG, freq, stack, T, U):
+    """For triangle pairs (T[b], U[b]), TRI(2) x TRI(2):
+    IA[b, i, j] = int int (r - v_i) . G_r(r, r') . (r' - v_j) and IS[b] = int int phi_r."""
+    from . import mgf
+    pts, w = _tri_rule(g)
+    q = pts.shape[1]
+    ro = np.repeat(pts[T], q, axis=1).reshape(-1, 3)
+    rs = np.tile(pts[U], (1, q, 1)).reshape(-1, 3)
+    G, ph = mgf.dyadic_reflected(stack, freq, ro, rs)
+    G = G.reshape(T.size, q, q, 3, 3)
+    ww = w[T][:, :, None] * w[U][:, None, :]
+    dt = pts[T][:, :, None, :] - g.verts[g.tris[T]][:, None, :, :]      # (B, q, 3 vertices, 3)
+    du = pts[U][:, :, None, :] - g.verts[g.tris[U]][:, None, :, :]
+    IA = np.einsum('bpq,bpia,bpqac,bqjc->bij', ww, dt, G, du)
+    IS = np.einsum('bpq,bpq->b', ww, ph.reshape(T.size, q, q))
+    return IA, IS
+
+
+def reflected_entries(g: RWG, freq, stack, m, n):
+    """Reflected part of L_A[m, n] (RWG pairs) from the triangle-pair integrals above."""
+    m = np.asarray(m)
+    n = np.asarray(n)
+    Tm = np.stack([g.tplus[m], g.tminus[m]], 1)
+    Tn = np.stack([g.tplus[n], g.tminus[n]], 1)
+    keys = np.unique(np.concatenate([np.stack([Tm[:, a], Tn[:, b]], 1) for a in range(2) for b in range(2)]), axis=0)
+    IA, _ = _reflected_pair_integrals(g, freq, stack, keys[:, 0], keys[:, 1])
+    key = keys[:, 0] * np.int64(g.n_t) + keys[:, 1]
+    out = np.zeros(m.size, dtype=complex)
+    for a in range(2):
+        for b in range(2):
+            t, u = Tm[:, a], Tn[:, b]
+            i = np.argmax(g.tri_edge[t] == m[:, None], axis=1)
+            j = np.argmax(g.tri_edge[u] == n[:, None], axis=1)
+            p = np.searchsorted(key, t * np.int64(g.n_t) + u)
+            out += (g.tri_sign[t, i] * g.tri_sign[u, j] * g.length[m] * g.length[n]
+                    / (4.0 * g.area[t] * g.area[u])) * IA[p, i, j]
+    return out
+
+
+def reflected_phi_entries(g: RWG, freq, stack, t, u):
+    """Reflected part of L_phi[t, u] = 1/(A_t A_u) int int phi_r, TRI(2) x TRI(2)."""
+    t = np.asarray(t)
+    u = np.asarray(u)
+    _, IS = _reflected_pair_integrals(g, freq, stack, t, u)
+    return IS / (g.area[t] * g.area[u])
+
+
+def _lattice_reflected(grid: Grid, freq, stack):
+    """Reflected kernels at every (|dx|, |dy|, iz + iz') of the grid: dict of (2Nz-1, Ny, Nx) arrays."""
+    from . import mgf
+    Nx, Ny, Nz = grid.N
+    z0 = grid.origin[2] - stack.z_if
+    if z0 <= 0:
+        raise ValueError("the AIM grid reaches below the interface")
+    s, iy, ix = np.meshgrid(np.arange(2 * Nz - 1), np.arange(Ny), np.arange(Nx), indexing='ij')
+    k = mgf.reflected(stack, freq, np.hypot(ix * grid.h[0], iy * grid.h[1]).ravel(),
+                      (2 * z0 + s * grid.h[2]).ravel())
+    return {key: v.reshape(s.shape) for key, v in k.items()}
+
+
+def grid_part_layered(grid: Grid, lat, cA, wA, cB, wB, m, n):
+    """Reflected grid part of near entries: sum over stencil node pairs of wA . G_r . wB.
+
+    wA/wB: (basis, 3, 27) RWG weights (dyadic) or (basis, 27) pulse weights (scalar kernel).
+    G_r between nodes i and j uses the in-plane offset i - j and the z-index sum.
+    """
+    out = np.zeros(m.size, dtype=complex)
+    for lo in range(0, m.size, 5000):
+        s = slice(lo, lo + 5000)
+        ni = (cA[m[s]][:, None, :] + OFFS[None])[:, :, None, :]                                    # (B,27,1,3)
+        nj = (cB[n[s]][:, None, :] + OFFS[None])[:, None, :, :]                                    # (B,1,27,3)
+        d = ni - nj
+        ax, ay = np.abs(d[..., 0]), np.abs(d[..., 1])
+        sz = ni[..., 2] + nj[..., 2]
+        if wA.ndim == 2:
+            G = lat["phi"][sz, ay, ax]
+            out[s] = np.einsum('bi,bij,bj->b', wA[m[s]], G, wB[n[s]])
+            continue
+        xx, zz, zx = lat["xx"][sz, ay, ax], lat["zz"][sz, ay, ax], lat["zx"][sz, ay, ax]
+        dx, dy = d[..., 0] * grid.h[0], d[..., 1] * grid.h[1]
+        r = np.hypot(dx, dy)
+        with np.errstate(invalid='ignore', divide='ignore'):
+            cx = np.where(r > 0, dx / r, 0.0)
+            cy = np.where(r > 0, dy / r, 0.0)
+        A, B = wA[m[s]], wB[n[s]]                       # (B,3,27)
+        v = np.einsum('bi,bij,bj->b', A[:, 0], xx, B[:, 0]) + np.einsum('bi,bij,bj->b', A[:, 1], xx, B[:, 1])
+        v += np.einsum('bi,bij,bj->b', A[:, 2], zz, B[:, 2])
+        v += np.einsum('bi,bij,bj->b', A[:, 2], cx * zx, B[:, 0]) - np.einsum('bi,bij,bj->b', A[:, 0], cx * zx, B[:, 2])
+        v += np.einsum('bi,bij,bj->b', A[:, 2], cy * zx, B[:, 1]) - np.einsum('bi,bij,bj->b', A[:, 1], cy * zx, B[:, 2])
+        out[s] = v
+    return out
+
+
+@dataclass
+class LayeredAIMOperator:
+    grid: Grid
+    freq: float
+    stack: object
+    Pc: list
+    Pr: object
+    LA_nr: object
+    Lphi_nr: object
+
+    def apply_LA(self, j):
+        S = np.zeros((4, self.grid.n_nodes), dtype=complex)
+        for c in range(3):
+            S[c] = self.Pc[c] @ j
+        Phi = convolve_layered_direct(self.grid, self.freq, self.stack, S)
+        return self.LA_nr @ j + sum(self.Pc[c].T @ Phi[c] for c in range(3))
+
+    def apply_Lphi(self, q):
+        S = np.zeros((4, self.grid.n_nodes), dtype=complex)
+        S[3] = self.Pr @ q
+        Phi = convolve_layered_direct(self.grid, self.freq, self.stack, S)
+        return self.Lphi_nr @ q + self.Pr.T @ Phi[3]
+
+
+def build_aim_layered(g: RWG, grid: Grid, freq, stack):
+    """AIM over a layered background: near entries = exact (free + reflected) - grid (free + reflected)."""
+    from . import mgf
+    k0 = 2.0 * np.pi * freq / mgf.C0
+    Pc, Pr, (cE, wE, _), (cT, wT, _) = projection_matrices(grid, g)
+    lat = _lattice_reflected(grid, freq, stack)
+    m, n = near_pairs(cE, cE)
+    vA = (exact_entries(g, k0, m, n) + reflected_entries(g, freq, stack, m, n)
+          - grid_part(grid, k0, cE, wE, cE, wE, m, n) - grid_part_layered(grid, lat, cE, wE, cE, wE, m, n))
+    t, u = near_pairs(cT, cT)
+    vP = (exact_phi_entries(g, k0, t, u) + reflected_phi_entries(g, freq, stack, t, u)
+          - grid_part(grid, k0, cT, wT, cT, wT, t, u) - grid_part_layered(grid, lat, cT, wT, cT, wT, t, u))
+    LA_nr = sp.csr_matrix((vA, (m, n)), shape=(g.n_e, g.n_e))
+    Lphi_nr = sp.csr_matrix((vP, (t, u)), shape=(g.n_t, g.n_t))
+    return LayeredAIMOperator(grid, freq, stack, Pc, Pr, LA_nr, Lphi_nr)
