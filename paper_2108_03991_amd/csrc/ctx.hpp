@@ -102,6 +102,7 @@ struct Ctx {
   double lay_zif = 0.0;
   int lay_nodes = 0;
   DevBuf d_lay_real, d_rhat128, d_rhat64, d_lay;
+  DevBuf d_nA_free, d_nP_free;          // free-space near values, kept once a medium changes them
   std::vector<int32_t> h_cidx_e, h_cidx_t;     // stencil centres (host copies)
   std::vector<double> h_w_e, h_w_t;            // stencil weights (host copies)
   // near field
@@ -167,7 +168,9 @@ void launch_pack_dense(const double* Acm, int64_t rows, int64_t cols, Cplx<float
 // fft.hip
 void fft_init_twiddles(Ctx& c);
 void fft_forward_3d_c128(Ctx& c, double* data_full, hipStream_t s);   // full (2N)^3 in place (build)
-void aim_convolve(Ctx& c, bool fp64, int ncomp, hipStream_t s, int comp0 = 0);   // oct_in -> oct_out
+// oct_in -> oct_out; layered: free-space kernel plus the reflected dyadic (components
+// {0,1,2}, {3} or all four)
+void aim_convolve(Ctx& c, bool fp64, int ncomp, hipStream_t s, int comp0 = 0, bool layered = false);
 void aim_convolve_layered(Ctx& c, bool fp64, hipStream_t s);   // oct_in -> oct_out, 4 components
 // layered.hip
 void build_layered(Ctx& c, const slim_medium& m, hipStream_t s);

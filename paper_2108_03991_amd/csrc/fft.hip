@@ -233,7 +233,7 @@ void launch_pass_L(int L, const PassArgs& a, int ncomp, hipStream_t s) {
 // spectra cover kx <= Nx, ky <= Ny (mirrored; zx odd in x, zy odd in y) and all kz.
 template <class T>
 __global__ void k_layered_mix(C2<T>* S, int64_t comp, const C2<T>* gp, const C2<T>* rh, int64_t spec, int Nx, int Ny,
-                              int Nz) {
+                              int Nz, int do_vec, int do_rho) {
   const int X2 = 2 * Nx, Y2 = 2 * Ny, Z2 = 2 * Nz;
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   const int64_t plane = int64_t(X2) * Y2;
@@ -243,11 +243,14 @@ __global__ void k_layered_mix(C2<T>* S, int64_t comp, const C2<T>* gp, const C2<
   const int mx = kx <= Nx ? kx : X2 - kx, my = ky <= Ny ? ky : Y2 - ky;
   const T sx = kx <= Nx ? T(1) : T(-1), sy = ky <= Ny ? T(1) : T(-1);
   const int64_t o1 = int64_t(k1) * plane + int64_t(ky) * X2 + kx, o2 = int64_t(k2) * plane + int64_t(ky) * X2 + kx;
+  // the vector components (0..2) and the charge (3) are independent products; a call
+  // may take either set (they then run on different streams)
   C2<T> a[4], b[4];
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
-    a[c] = S[c * comp + o1];
-    b[c] = S[c * comp + o2];
+    const bool use = c < 3 ? do_vec : do_rho;
+    a[c] = use ? S[c * comp + o1] : C2<T>{T(0), T(0)};
+    b[c] = use ? S[c * comp + o2] : C2<T>{T(0), T(0)};
   }
   auto product = [&](int kz, const C2<T>* self, const C2<T>* part, C2<T>* r) {
     const int mz = kz <= Nz ? kz : Z2 - kz;
@@ -268,6 +271,7 @@ __global__ void k_layered_mix(C2<T>* S, int64_t comp, const C2<T>* gp, const C2<
   product(k2, b, a, r2);
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
+    if (c < 3 ? !do_vec : !do_rho) continue;
     S[c * comp + o1] = r1[c];
     S[c * comp + o2] = r2[c];
   }
@@ -369,7 +373,10 @@ static void convolve_impl(Ctx& c, bool fp64, int ncomp, hipStream_t s, int comp0
     } else {
       // layered z step: forward into the full-z work array, spectrum product with
       // the partner -kz, inverse back (keep z < Nz)
-      char* lay = reinterpret_cast<char*>(c.d_lay.p);
+      SLIM_REQUIRE((comp0 == 0 && (ncomp == 3 || ncomp == 4)) || (comp0 == 3 && ncomp == 1), SLIM_E_ARG,
+                   "layered convolution takes the vector components, the charge, or all four");
+      char* lay0 = reinterpret_cast<char*>(c.d_lay.p);
+      char* lay = lay0 + size_t(comp0) * 8 * N3 * esz;
       a = PassArgs{};
       a.in = x2; a.out = lay;
       a.in_e = a.out_e = int64_t(X2) * Y2; a.in_o1 = a.out_o1 = 1; a.in_o2 = a.out_o2 = X2;
@@ -380,9 +387,10 @@ static void convolve_impl(Ctx& c, bool fp64, int ncomp, hipStream_t s, int comp0
       const int64_t pairs = int64_t(X2) * Y2 * (Nz + 1);
       const int64_t spec = int64_t(Nx + 1) * (Ny + 1) * Z2;
       hipLaunchKernelGGL((k_layered_mix<T>), dim3(unsigned((pairs + 255) / 256)), dim3(256), 0, s,
-                         reinterpret_cast<C2<T>*>(lay), 8 * N3,
+                         reinterpret_cast<C2<T>*>(lay0), 8 * N3,
                          reinterpret_cast<const C2<T>*>(fp64 ? c.d_ghat128.p : c.d_ghat64.p),
-                         reinterpret_cast<const C2<T>*>(fp64 ? c.d_rhat128.p : c.d_rhat64.p), spec, Nx, Ny, Nz);
+                         reinterpret_cast<const C2<T>*>(fp64 ? c.d_rhat128.p : c.d_rhat64.p), spec, Nx, Ny, Nz,
+                         comp0 == 0 ? 1 : 0, comp0 + ncomp == 4 ? 1 : 0);
       SLIM_HIP(hipGetLastError());
       a = PassArgs{};
       a.in = lay; a.out = x2;
@@ -415,8 +423,9 @@ static void convolve_impl(Ctx& c, bool fp64, int ncomp, hipStream_t s, int comp0
   else run(float{});
 }
 
-void aim_convolve(Ctx& c, bool fp64, int ncomp, hipStream_t s, int comp0) {
-  convolve_impl(c, fp64, ncomp, s, comp0, false);
+void aim_convolve(Ctx& c, bool fp64, int ncomp, hipStream_t s, int comp0, bool layered) {
+  SLIM_REQUIRE(!layered || c.layered, SLIM_E_STATE, "no layered medium set");
+  convolve_impl(c, fp64, ncomp, s, comp0, layered);
 }
 
 // The four components over a layered background (free-space kernel plus the

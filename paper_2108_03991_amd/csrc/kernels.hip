@@ -497,7 +497,7 @@ void matvec_t(Ctx& c, const void* x, void* y, void* e_out, void* g_out, void* a_
                        int64_t(0), c.d_pt_node.as<int32_t>(), c.d_pt_ptr.as<int32_t>(), c.d_pt_idx.as<int32_t>(),
                        F64 ? c.d_pt_w64.p : c.d_pt_w32.p, c.n_pt_nodes, nullptr, rho, oct_in, N3);
     SLIM_HIP(hipGetLastError());
-    aim_convolve(c, F64, 1, st, 3);
+    aim_convolve(c, F64, 1, st, 3, c.layered);
     hipLaunchKernelGGL(k_phi<F64>, dim3(nblk(nt, 4)), dim3(256), 0, st, c.d_wt_base.as<int32_t>(),
                        F64 ? c.d_wt_w64.p : c.d_wt_w32.p, c.d_oct_out.p, N3, Nx, NxNy, c.d_nP_ptr.as<int64_t>(),
                        c.d_nP_col.as<int32_t>(), F64 ? c.d_nP_v128.p : c.d_nP_v64.p, rho, c.d_phi.p, nt);
@@ -533,7 +533,7 @@ void matvec_t(Ctx& c, const void* x, void* y, void* e_out, void* g_out, void* a_
     SLIM_HIP(hipGetLastError());
     mark(1);
     mark(2);
-    aim_convolve(c, F64, overlap ? 3 : 4, s);
+    aim_convolve(c, F64, overlap ? 3 : 4, s, 0, c.layered);
     mark(2);
     mark(3);
     if (overlap) {

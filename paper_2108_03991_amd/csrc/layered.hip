@@ -135,6 +135,7 @@ struct LatArgs {
   int Nx, Ny, S;         // lattice: |ix| < Nx, |iy| < Ny, S zeta values
   double hx, hy, hz, zeta0, k0;
   double2 cxx, czz, cphi, czx;
+  int table;             // 1: rho = ix hx (Ny = 1) and only the integrated remainders are written
   double2* out;          // [4][S][Ny][Nx]
 };
 
@@ -227,6 +228,11 @@ __global__ void __launch_bounds__(256) k_refl_lattice(LatArgs a) {
     const double2 img = make_double2(f * cs / R, -f * sn / R);
     const double st = f * rho / (R * (R + zeta[q]));
     const int64_t o = (int64_t(s) * a.Ny + iy) * a.Nx + ix, plane = int64_t(a.S) * npts;
+    if (a.table) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) a.out[k * plane + o] = make_double2(f * acc[k][q].x, f * acc[k][q].y);
+      continue;
+    }
     a.out[o] = ca(cm(a.cxx, img), make_double2(f * acc[0][q].x, f * acc[0][q].y));
     a.out[plane + o] = ca(cm(a.czz, img), make_double2(f * acc[1][q].x, f * acc[1][q].y));
     a.out[2 * plane + o] = ca(cm(a.cphi, img), make_double2(f * acc[2][q].x, f * acc[2][q].y));
@@ -276,16 +282,269 @@ __global__ void k_refl_spectrum(const double2* full, int Nx, int Ny, int Nz, dou
 
 }  // namespace
 
+namespace {
+
+// Quadrature path and node table for offsets up to rho_max and zeta >= zmin: per node
+// (kr, kz, Exx, Ezz, Ephi, Ezx, Wzx), the weighted remainders of the four spectral factors.
+struct Limits { cd cxx, czz, cphi, czx; };
+
+std::vector<cd> node_table(const Stack& st, double w, double k0, double rho_max, double zmin, const Limits& L) {
+  double kre = k0;
+  for (const slim_layer& Ly : st.layers)
+    kre = std::max(kre, std::abs((w * std::sqrt(kMu0 * eps_c(w, Ly.eps_r, Ly.sigma))).real()));
+  if (!st.pec) kre = std::max(kre, std::abs((w * std::sqrt(kMu0 * eps_c(w, st.eb, st.sb))).real()));
+  const double a = 2.5 * kre + k0;
+  const double b = std::min(0.4 * a, 1.0 / rho_max);
+  SLIM_REQUIRE(std::hypot(a, b) * rho_max <= 8.0, SLIM_E_UNSUPPORTED,
+               "layered kernels: the grid spans too many substrate wavelengths for the quadrature path");
+  const double k_end = a + 40.0 / zmin;
+  const double dk_max = std::min(0.5 * kPi / rho_max, 0.25 / zmin);
+  std::vector<double> gx, gw;
+  gauss_legendre(8, gx, gw);
+  std::vector<cd> kr, wk;
+  const int n_arc = 48;
+  for (int pnl = 0; pnl < n_arc; ++pnl) {
+    const double t0 = a * pnl / n_arc, t1 = a * (pnl + 1) / n_arc;
+    for (int i = 0; i < 8; ++i) {
+      const double t = 0.5 * (t1 - t0) * (gx[i] + 1.0) + t0;
+      kr.push_back(cd(t, b * std::sin(kPi * t / a)));
+      wk.push_back(0.5 * (t1 - t0) * gw[i] * cd(1.0, b * kPi / a * std::cos(kPi * t / a)));
+    }
+  }
+  for (double lo = a, width = 0.25 * k0; lo < k_end; width *= 1.6) {
+    const double hi = std::min(k_end, lo + std::min(width, dk_max));
+    for (int i = 0; i < 8; ++i) {
+      kr.push_back(cd(0.5 * (hi - lo) * (gx[i] + 1.0) + lo, 0.0));
+      wk.push_back(cd(0.5 * (hi - lo) * gw[i], 0.0));
+    }
+    lo = hi;
+  }
+  const size_t n_nodes = kr.size();
+  std::vector<cd> tab(n_nodes * 7);
+  for (size_t n = 0; n < n_nodes; ++n) {
+    cd ge, gh;
+    reflection(st, w, kr[n], ge, gh);
+    const cd k = kr[n], kz = kz_of(cd(k0 * k0, 0.0), k);
+    const cd j0w = wk[n] * k / (cd(0.0, 1.0) * kz);
+    const cd fzz = (ge * (kz * kz - k * k) - gh * kz * kz) / (k * k);
+    const cd fph = (k0 * k0 * gh - kz * kz * ge) / (k * k);
+    cd* r = &tab[n * 7];
+    r[0] = k;
+    r[1] = kz;
+    r[2] = (gh - L.cxx) * j0w;
+    r[3] = (fzz - L.czz) * j0w;
+    r[4] = (fph - L.cphi) * j0w;
+    r[5] = (ge - gh - L.czx) * wk[n];
+    r[6] = L.czx * wk[n];
+  }
+  return tab;
+}
+
+double2 d2(cd v) { return make_double2(v.real(), v.imag()); }
+
+// ---- reflected near field ----------------------------------------------------------
+// Interpolation table of the integrated remainders over (rho, zeta): [4][nz][nr]
+// (xx, zz, phi, zx), rows at zeta = z0 + j dz, columns at rho = i dr.  Cubic
+// Lagrange in both directions; rho < 0 mirrors (even kernels, odd zx remainder).
+struct Tab {
+  const double2* v;
+  int nr, nz;
+  double dr, z0, dz;
+};
+
+__device__ __forceinline__ void lag4(double t, double* L) {
+  L[0] = -t * (t - 1.0) * (t - 2.0) / 6.0;
+  L[1] = (t + 1.0) * (t - 1.0) * (t - 2.0) / 2.0;
+  L[2] = -(t + 1.0) * t * (t - 2.0) / 2.0;
+  L[3] = (t + 1.0) * t * (t - 1.0) / 6.0;
+}
+
+struct Kern { double2 xx, zz, ph, zx; };   // zx: radial factor
+
+__device__ Kern kern_at(const Tab& T, double rho, double zeta, double k0, const double2* lim) {
+  int i = int(floor(rho / T.dr));
+  i = min(i, T.nr - 3);
+  const double t = rho / T.dr - i;
+  int j = int(floor((zeta - T.z0) / T.dz));
+  j = max(1, min(j, T.nz - 3));
+  const double u = (zeta - T.z0) / T.dz - j;
+  double Lr[4], Lz[4];
+  lag4(t, Lr);
+  lag4(u, Lz);
+  double2 acc[4] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
+  const int64_t plane = int64_t(T.nr) * T.nz;
+  for (int b = 0; b < 4; ++b) {
+    const int64_t row = int64_t(j - 1 + b) * T.nr;
+    for (int a = 0; a < 4; ++a) {
+      int ii = i - 1 + a;
+      const double sgn = ii < 0 ? -1.0 : 1.0;
+      ii = ii < 0 ? -ii : ii;
+      const double wgt = Lr[a] * Lz[b];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const double2 v = T.v[k * plane + row + ii];
+        const double s = (k == 3 ? sgn : 1.0) * wgt;
+        acc[k].x += s * v.x;
+        acc[k].y += s * v.y;
+      }
+    }
+  }
+  // closed-form large-k_rho parts
+  const double R = sqrt(rho * rho + zeta * zeta), f = 1.0 / (4.0 * kPi);
+  double sn, cs;
+  sincos(k0 * R, &sn, &cs);
+  const double2 img = make_double2(f * cs / R, -f * sn / R);
+  const double st = f * rho / (R * (R + zeta));
+  Kern K;
+  K.xx = ca(cm(lim[0], img), acc[0]);
+  K.zz = ca(cm(lim[1], img), acc[1]);
+  K.ph = ca(cm(lim[2], img), acc[2]);
+  K.zx = make_double2(lim[3].x * st + acc[3].x, lim[3].y * st + acc[3].y);
+  return K;
+}
+
+struct NearRefl {
+  const double* xyz; const int32_t* tri; const int32_t* tri_edge; const int8_t* tri_sign;
+  const double* len; const double* area; const int32_t* tplus; const int32_t* tminus;
+  const int32_t* rows; const int32_t* cols; int64_t nnz;
+  const int32_t* cidx; const double* w;     // stencil centres and weights (3 x 27 RWG, 27 pulse)
+  const double2* lat; int Nx, Ny, S;        // lattice kernels [4][S][Ny][Nx]
+  double hx, hy, zif, k0;
+  Tab tab;
+  double2 lim[4];
+  int rwg;
+  double2* vals;                            // near values (complex128): += exact - grid, reflected
+};
+
+// TRI(2) on a triangle: P_k = V0 + u e1 + v (1-u) e2, weight w_u w_v (1-u) 2A
+__device__ void tri2(const double* xyz, const int32_t* tri, int t, double P[4][3], double W[4], double area) {
+  const double g0 = 0.5 - 0.5 / sqrt(3.0), g1 = 0.5 + 0.5 / sqrt(3.0);
+  const double* v0 = xyz + 3 * tri[3 * t];
+  const double* v1 = xyz + 3 * tri[3 * t + 1];
+  const double* v2 = xyz + 3 * tri[3 * t + 2];
+  for (int k = 0; k < 4; ++k) {
+    const double u = (k / 2) ? g1 : g0, v = (k % 2) ? g1 : g0;
+    for (int d = 0; d < 3; ++d) P[k][d] = v0[d] + u * (v1[d] - v0[d]) + v * (1.0 - u) * (v2[d] - v0[d]);
+    W[k] = 0.25 * (1.0 - u) * 2.0 * area;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_near_refl(NearRefl g) {
+  const int64_t z = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (z >= g.nnz) return;
+  const int m = g.rows[z], n = g.cols[z];
+  double2 ex = make_double2(0.0, 0.0);
+  // ---- exact reflected part, TRI(2) x TRI(2) ----
+  for (int sa = 0; sa < (g.rwg ? 2 : 1); ++sa) {
+    const int t = g.rwg ? (sa ? g.tminus[m] : g.tplus[m]) : m;
+    double Pt[4][3], Wt[4], ft[4][3];
+    tri2(g.xyz, g.tri, t, Pt, Wt, g.area[t]);
+    if (g.rwg) {
+      int i = 0;
+      while (g.tri_edge[3 * t + i] != m) ++i;
+      const double* vt = g.xyz + 3 * g.tri[3 * t + i];
+      const double cm_ = g.tri_sign[3 * t + i] * g.len[m] / (2.0 * g.area[t]);
+      for (int k = 0; k < 4; ++k)
+        for (int d = 0; d < 3; ++d) ft[k][d] = cm_ * (Pt[k][d] - vt[d]);
+    }
+    for (int sb = 0; sb < (g.rwg ? 2 : 1); ++sb) {
+      const int u = g.rwg ? (sb ? g.tminus[n] : g.tplus[n]) : n;
+      double Pu[4][3], Wu[4], fu[4][3];
+      tri2(g.xyz, g.tri, u, Pu, Wu, g.area[u]);
+      if (g.rwg) {
+        int j = 0;
+        while (g.tri_edge[3 * u + j] != n) ++j;
+        const double* vu = g.xyz + 3 * g.tri[3 * u + j];
+        const double cn_ = g.tri_sign[3 * u + j] * g.len[n] / (2.0 * g.area[u]);
+        for (int k = 0; k < 4; ++k)
+          for (int d = 0; d < 3; ++d) fu[k][d] = cn_ * (Pu[k][d] - vu[d]);
+      }
+      for (int k = 0; k < 4; ++k)
+        for (int l = 0; l < 4; ++l) {
+          const double dx = Pt[k][0] - Pu[l][0], dy = Pt[k][1] - Pu[l][1];
+          const double rho = sqrt(dx * dx + dy * dy), zeta = Pt[k][2] + Pu[l][2] - 2.0 * g.zif;
+          const Kern K = kern_at(g.tab, rho, zeta, g.k0, g.lim);
+          const double ww = Wt[k] * Wu[l];
+          if (g.rwg) {
+            const double* A = ft[k];
+            const double* B = fu[l];
+            const double cx = rho > 0.0 ? dx / rho : 0.0, cy = rho > 0.0 ? dy / rho : 0.0;
+            const double sxy = A[0] * B[0] + A[1] * B[1], szz = A[2] * B[2];
+            const double sc = cx * (A[2] * B[0] - A[0] * B[2]) + cy * (A[2] * B[1] - A[1] * B[2]);
+            ex.x += ww * (K.xx.x * sxy + K.zz.x * szz + K.zx.x * sc);
+            ex.y += ww * (K.xx.y * sxy + K.zz.y * szz + K.zx.y * sc);
+          } else {
+            ex.x += ww * K.ph.x;
+            ex.y += ww * K.ph.y;
+          }
+        }
+    }
+  }
+  if (!g.rwg) {   // L_phi = 1/(A_t A_u) int int phi_r
+    ex.x /= g.area[m] * g.area[n];
+    ex.y /= g.area[m] * g.area[n];
+  }
+  // ---- grid part of the reflected kernels over the two stencils ----
+  double2 gp = make_double2(0.0, 0.0);
+  const int nc = g.rwg ? 3 : 1;
+  const double* wm = g.w + int64_t(m) * 27 * nc;
+  const double* wn = g.w + int64_t(n) * 27 * nc;
+  const int64_t plane = int64_t(g.S) * g.Nx * g.Ny;
+  for (int a = 0; a < 27; ++a) {
+    const int ax = g.cidx[3 * m] + a % 3 - 1, ay = g.cidx[3 * m + 1] + (a / 3) % 3 - 1, az = g.cidx[3 * m + 2] + a / 9 - 1;
+    for (int b = 0; b < 27; ++b) {
+      const int bx = g.cidx[3 * n] + b % 3 - 1, by = g.cidx[3 * n + 1] + (b / 3) % 3 - 1,
+                bz = g.cidx[3 * n + 2] + b / 9 - 1;
+      const int ox = ax - bx, oy = ay - by;
+      const int64_t o = (int64_t(az + bz) * g.Ny + (oy < 0 ? -oy : oy)) * g.Nx + (ox < 0 ? -ox : ox);
+      if (g.rwg) {
+        const double2 xx = g.lat[o], zz = g.lat[plane + o], zx = g.lat[3 * plane + o];
+        const double dx = ox * g.hx, dy = oy * g.hy, r = sqrt(dx * dx + dy * dy);
+        const double cx = r > 0.0 ? dx / r : 0.0, cy = r > 0.0 ? dy / r : 0.0;
+        const double A0 = wm[a], A1 = wm[27 + a], A2 = wm[54 + a], B0 = wn[b], B1 = wn[27 + b], B2 = wn[54 + b];
+        const double sxy = A0 * B0 + A1 * B1, szz = A2 * B2;
+        const double sc = cx * (A2 * B0 - A0 * B2) + cy * (A2 * B1 - A1 * B2);
+        gp.x += xx.x * sxy + zz.x * szz + zx.x * sc;
+        gp.y += xx.y * sxy + zz.y * szz + zx.y * sc;
+      } else {
+        const double2 ph = g.lat[2 * plane + o];
+        const double ab = wm[a] * wn[b];
+        gp.x += ph.x * ab;
+        gp.y += ph.y * ab;
+      }
+    }
+  }
+  // the pulse near values carry the column factor A_u
+  const double sc = g.rwg ? 1.0 : g.area[n];
+  g.vals[z].x += sc * (ex.x - gp.x);
+  g.vals[z].y += sc * (ex.y - gp.y);
+}
+
+__global__ void k_expand_rows(const int64_t* ptr, int64_t nrows, int32_t* rows) {
+  const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (r >= nrows) return;
+  for (int64_t k = ptr[r]; k < ptr[r + 1]; ++k) rows[k] = int32_t(r);
+}
+
+__global__ void k_c128_to_c64_n(const double2* in, float2* out, int64_t n) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = make_float2(float(in[i].x), float(in[i].y));
+}
+
+}  // namespace
+
 void build_layered(Ctx& c, const slim_medium& md, hipStream_t s) {
   SLIM_REQUIRE(c.built && !c.plain, SLIM_E_STATE, "no AIM operator built");
   SLIM_REQUIRE(md.n_layers >= 0 && (md.n_layers == 0 || md.layers), SLIM_E_ARG, "bad layer list");
   Stack st;
+  double d_min = 1e300;
   for (int l = 0; l < md.n_layers; ++l) {
     const slim_layer& L = md.layers[l];
     SLIM_REQUIRE(std::isfinite(L.thickness) && L.thickness > 0 && std::isfinite(L.eps_r) && L.eps_r > 0 &&
                      std::isfinite(L.sigma) && L.sigma >= 0,
                  SLIM_E_ARG, "layer " + std::to_string(l) + ": thickness > 0, eps_r > 0, sigma >= 0");
     st.layers.push_back(L);
+    d_min = std::min(d_min, L.thickness);
   }
   st.pec = md.bottom_pec != 0;
   if (!st.pec) {
@@ -301,74 +560,23 @@ void build_layered(Ctx& c, const slim_medium& md, hipStream_t s) {
                "the AIM grid reaches the interface: its lowest node must lie above z_interface");
   const int Nx = G.N[0], Ny = G.N[1], Nz = G.N[2];
   const double w = c.omega, k0 = c.k0;
-  // ---- quadrature path ----
-  double kre = k0;
-  for (const slim_layer& L : st.layers) kre = std::max(kre, std::abs((w * std::sqrt(kMu0 * eps_c(w, L.eps_r, L.sigma))).real()));
-  if (!st.pec) kre = std::max(kre, std::abs((w * std::sqrt(kMu0 * eps_c(w, st.eb, st.sb))).real()));
-  const double a = 2.5 * kre + k0;
-  const double rho_max = std::sqrt(std::pow((Nx - 1) * G.h[0], 2) + std::pow((Ny - 1) * G.h[1], 2));
-  const double b = std::min(0.4 * a, 1.0 / rho_max);
-  SLIM_REQUIRE(std::hypot(a, b) * rho_max <= 8.0, SLIM_E_UNSUPPORTED,
-               "layered grid kernels: the grid spans too many substrate wavelengths for the quadrature path");
-  const double zmin = 2.0 * z0;
-  const double k_end = a + 40.0 / zmin;
-  const double dk_max = std::min(0.5 * kPi / rho_max, 0.25 / zmin);
-  std::vector<double> gx, gw;
-  gauss_legendre(8, gx, gw);
-  std::vector<cd> kr, wk;
-  const int n_arc = 48;
-  for (int pnl = 0; pnl < n_arc; ++pnl) {
-    const double t0 = a * pnl / n_arc, t1 = a * (pnl + 1) / n_arc;
-    for (int i = 0; i < 8; ++i) {
-      const double t = 0.5 * (t1 - t0) * (gx[i] + 1.0) + t0;
-      kr.push_back(cd(t, b * std::sin(kPi * t / a)));
-      wk.push_back(0.5 * (t1 - t0) * gw[i] * cd(1.0, b * kPi / a * std::cos(kPi * t / a)));
-    }
-  }
-  {
-    double lo = a, width = 0.25 * k0;
-    while (lo < k_end) {
-      const double hi = std::min(k_end, lo + std::min(width, dk_max));
-      for (int i = 0; i < 8; ++i) {
-        kr.push_back(cd(0.5 * (hi - lo) * (gx[i] + 1.0) + lo, 0.0));
-        wk.push_back(cd(0.5 * (hi - lo) * gw[i], 0.0));
-      }
-      lo = hi;
-      width *= 1.6;
-    }
-  }
+  c.layered = false;
+  c.drop_graphs();   // captured products hold the free-space convolution
   // ---- large-k_rho limits: the medium right below the interface seen as a half-space ----
   cd ge_inf, gh_inf;
-  {
-    bool top_pec = st.layers.empty() && st.pec;
-    if (top_pec) {
-      ge_inf = gh_inf = cd(-1.0, 0.0);
-    } else {
-      const cd e1 = st.layers.empty() ? eps_c(w, st.eb, st.sb) : eps_c(w, st.layers[0].eps_r, st.layers[0].sigma);
-      ge_inf = (eps0() - e1) / (eps0() + e1);
-      gh_inf = cd(0.0, 0.0);
-    }
+  if (st.layers.empty() && st.pec) {
+    ge_inf = gh_inf = cd(-1.0, 0.0);
+  } else {
+    const cd e1 = st.layers.empty() ? eps_c(w, st.eb, st.sb) : eps_c(w, st.layers[0].eps_r, st.layers[0].sigma);
+    ge_inf = (eps0() - e1) / (eps0() + e1);
+    gh_inf = cd(0.0, 0.0);
   }
-  const cd cxx = gh_inf, czz = -2.0 * ge_inf + gh_inf, cphi = ge_inf, czx = ge_inf - gh_inf;
-  // ---- node table ----
-  const int n_nodes = int(kr.size());
-  std::vector<cd> tab(size_t(n_nodes) * 7);
-  for (int n = 0; n < n_nodes; ++n) {
-    cd ge, gh;
-    reflection(st, w, kr[n], ge, gh);
-    const cd k = kr[n], kz = kz_of(cd(k0 * k0, 0.0), k);
-    const cd j0w = wk[n] * k / (cd(0.0, 1.0) * kz);
-    const cd fzz = (ge * (kz * kz - k * k) - gh * kz * kz) / (k * k);
-    const cd fph = (k0 * k0 * gh - kz * kz * ge) / (k * k);
-    cd* r = &tab[size_t(n) * 7];
-    r[0] = k;
-    r[1] = kz;
-    r[2] = (gh - cxx) * j0w;
-    r[3] = (fzz - czz) * j0w;
-    r[4] = (fph - cphi) * j0w;
-    r[5] = (ge - gh - czx) * wk[n];
-    r[6] = czx * wk[n];
-  }
+  Limits lim{gh_inf, -2.0 * ge_inf + gh_inf, ge_inf, ge_inf - gh_inf};
+  // ---- kernels on the grid lattice ----
+  const double rho_max = std::sqrt(std::pow((Nx - 1) * G.h[0], 2) + std::pow((Ny - 1) * G.h[1], 2));
+  const double zmin = 2.0 * z0;
+  std::vector<cd> tab = node_table(st, w, k0, rho_max, zmin, lim);
+  const int n_nodes = int(tab.size() / 7);
   DevBuf d_tab;
   d_tab.alloc(tab.size() * 16);
   SLIM_HIP(hipMemcpy(d_tab.p, tab.data(), tab.size() * 16, hipMemcpyHostToDevice));
@@ -380,13 +588,10 @@ void build_layered(Ctx& c, const slim_medium& md, hipStream_t s) {
   la.Nx = Nx; la.Ny = Ny; la.S = int(Si);
   la.hx = G.h[0]; la.hy = G.h[1]; la.hz = G.h[2];
   la.zeta0 = zmin; la.k0 = k0;
-  la.cxx = make_double2(cxx.real(), cxx.imag());
-  la.czz = make_double2(czz.real(), czz.imag());
-  la.cphi = make_double2(cphi.real(), cphi.imag());
-  la.czx = make_double2(czx.real(), czx.imag());
+  la.cxx = d2(lim.cxx); la.czz = d2(lim.czz); la.cphi = d2(lim.cphi); la.czx = d2(lim.czx);
+  la.table = 0;
   la.out = c.d_lay_real.as<double2>();
-  const int64_t nthreads = npts * ((Si + kZT - 1) / kZT);
-  hipLaunchKernelGGL(k_refl_lattice, dim3(nblk(nthreads)), dim3(256), 0, s, la);
+  hipLaunchKernelGGL(k_refl_lattice, dim3(nblk(npts * ((Si + kZT - 1) / kZT))), dim3(256), 0, s, la);
   SLIM_HIP(hipGetLastError());
   // ---- spectra: xx, zz, phi, zx, zy ----
   const int64_t full = int64_t(8) * G.nodes();
@@ -409,6 +614,74 @@ void build_layered(Ctx& c, const slim_medium& md, hipStream_t s) {
     SLIM_HIP(hipStreamSynchronize(s));
   }
   c.d_lay.alloc(size_t(4 * full) * 16);
+  // ---- near field: exact reflected part minus its grid part, on the existing CSRs ----
+  if (c.nnz_A + c.nnz_P > 0) {
+    // table of the integrated remainders over the grid's (rho, zeta) range
+    const double zlo = 2.0 * z0, zhi = 2.0 * z0 + 2.0 * (Nz - 1) * G.h[2];
+    double dlt = std::min(z0, d_min / 16.0);
+    double kmax = k0;
+    for (const slim_layer& Ly : st.layers) kmax = std::max(kmax, std::abs(w * std::sqrt(kMu0 * eps_c(w, Ly.eps_r, Ly.sigma))));
+    dlt = std::min(dlt, 0.3 / kmax);
+    dlt = std::max({dlt, rho_max / 2000.0, (zhi - zlo) / 2000.0});
+    const int nr = int(std::ceil(rho_max / dlt)) + 3, nz = int(std::ceil((zhi - zlo) / dlt)) + 4;
+    const double tz0 = zlo - dlt;
+    std::vector<cd> tab2 = node_table(st, w, k0, (nr - 1) * dlt, tz0, lim);
+    DevBuf d_tab2, d_rt;
+    d_tab2.alloc(tab2.size() * 16);
+    SLIM_HIP(hipMemcpy(d_tab2.p, tab2.data(), tab2.size() * 16, hipMemcpyHostToDevice));
+    d_rt.alloc(size_t(4) * nr * nz * 16);
+    LatArgs ta = la;
+    ta.node = d_tab2.as<double2>();
+    ta.n_nodes = int(tab2.size() / 7);
+    ta.Nx = nr; ta.Ny = 1; ta.S = nz;
+    ta.hx = dlt; ta.hy = 0.0; ta.hz = dlt; ta.zeta0 = tz0;
+    ta.table = 1;
+    ta.out = d_rt.as<double2>();
+    hipLaunchKernelGGL(k_refl_lattice, dim3(nblk(int64_t(nr) * ((nz + kZT - 1) / kZT))), dim3(256), 0, s, ta);
+    SLIM_HIP(hipGetLastError());
+    DevBuf d_cidx, d_rows;
+    for (int which = 0; which < 2; ++which) {
+      const bool rwg = which == 0;
+      const int64_t nnz = rwg ? c.nnz_A : c.nnz_P, nrows = rwg ? c.rwg.n_e : c.rwg.n_t;
+      if (nnz == 0) continue;
+      DevBuf& v128 = rwg ? c.d_nA_v128 : c.d_nP_v128;
+      DevBuf& v64 = rwg ? c.d_nA_v64 : c.d_nP_v64;
+      DevBuf& fr = rwg ? c.d_nA_free : c.d_nP_free;
+      // keep the free-space values once; a later medium starts again from them
+      if (!fr.p) {
+        fr.alloc(v128.bytes);
+        SLIM_HIP(hipMemcpyAsync(fr.p, v128.p, v128.bytes, hipMemcpyDeviceToDevice, s));
+      } else {
+        SLIM_HIP(hipMemcpyAsync(v128.p, fr.p, v128.bytes, hipMemcpyDeviceToDevice, s));
+      }
+      const std::vector<int32_t>& ci = rwg ? c.h_cidx_e : c.h_cidx_t;
+      d_cidx.alloc(ci.size() * 4);
+      SLIM_HIP(hipMemcpy(d_cidx.p, ci.data(), ci.size() * 4, hipMemcpyHostToDevice));
+      d_rows.alloc(size_t(nnz) * 4);
+      const DevBuf& ptr = rwg ? c.d_nA_ptr : c.d_nP_ptr;
+      hipLaunchKernelGGL(k_expand_rows, dim3(nblk(nrows)), dim3(256), 0, s, ptr.as<int64_t>(), nrows,
+                         d_rows.as<int32_t>());
+      SLIM_HIP(hipGetLastError());
+      NearRefl nr_{};
+      nr_.xyz = c.d_xyz.as<double>(); nr_.tri = c.d_tri.as<int32_t>(); nr_.tri_edge = c.d_tri_edge.as<int32_t>();
+      nr_.tri_sign = c.d_tri_sign.as<int8_t>(); nr_.len = c.d_len.as<double>(); nr_.area = c.d_area.as<double>();
+      nr_.tplus = c.d_tplus.as<int32_t>(); nr_.tminus = c.d_tminus.as<int32_t>();
+      nr_.rows = d_rows.as<int32_t>(); nr_.cols = (rwg ? c.d_nA_col : c.d_nP_col).as<int32_t>(); nr_.nnz = nnz;
+      nr_.cidx = d_cidx.as<int32_t>(); nr_.w = (rwg ? c.d_we_w64 : c.d_wt_w64).as<double>();
+      nr_.lat = c.d_lay_real.as<double2>(); nr_.Nx = Nx; nr_.Ny = Ny; nr_.S = int(Si);
+      nr_.hx = G.h[0]; nr_.hy = G.h[1]; nr_.zif = md.z_interface; nr_.k0 = k0;
+      nr_.tab = Tab{d_rt.as<double2>(), nr, nz, dlt, tz0, dlt};
+      nr_.lim[0] = d2(lim.cxx); nr_.lim[1] = d2(lim.czz); nr_.lim[2] = d2(lim.cphi); nr_.lim[3] = d2(lim.czx);
+      nr_.rwg = rwg ? 1 : 0;
+      nr_.vals = v128.as<double2>();
+      hipLaunchKernelGGL(k_near_refl, dim3(nblk(nnz)), dim3(256), 0, s, nr_);
+      SLIM_HIP(hipGetLastError());
+      hipLaunchKernelGGL(k_c128_to_c64_n, dim3(nblk(nnz)), dim3(256), 0, s, v128.as<double2>(), v64.as<float2>(), nnz);
+      SLIM_HIP(hipGetLastError());
+      SLIM_HIP(hipStreamSynchronize(s));
+    }
+  }
+  SLIM_HIP(hipStreamSynchronize(s));
   c.layered = true;
   c.lay_zif = md.z_interface;
   c.lay_nodes = n_nodes;
