@@ -224,13 +224,16 @@ def layered_bytes(N, mixed):
 
 
 def layered_study(steps=10, warmup=2):
-    """The layered-medium grid convolution on the bundle-over-substrate workload.
+    """The bundle-over-substrate workload: the layered product and its convolution.
 
     The 200-line bundle (1 GHz, AIM grid 128^3) sits above a silicon substrate
     (200 um, eps_r 11.9, sigma 10 S/m) on a PEC ground.  The interface is 1 um
-    below the lowest grid plane.  The reflected kernels are built once, then the
-    four-component convolution (free space + reflected) is timed per entry-point
-    call, against the free-space convolution of the same four components.
+    below the lowest grid plane.  Timed:
+      * the whole product (default path) before and after the medium is set;
+      * the four-component convolution per entry-point call, layered against
+        free space.
+    Setting the medium builds the reflected lattice kernels and corrects the
+    near field.
     """
     import torch
     from paper_2108_03991_amd import slim
@@ -239,17 +242,40 @@ def layered_study(steps=10, warmup=2):
     mesh = make_mesh("line_bundle", kw)
     ctx = slim.Context(0)
     ctx.set_mesh(mesh.verts, mesh.tris, mesh.obj, mesh.n_obj)
-    lay = ctx.build(freq=freq, grid=grid, precond=0)
+    lay = ctx.build(freq=freq, grid=grid, precond=0, verbose=1)
+    x = torch.tensor(random_complex(lay.n_sys, 7), dtype=torch.complex128, device="cuda")
+    y = torch.zeros_like(x)
+    y64 = torch.zeros_like(x)
+
+    def product_ms(prec, out):
+        for _ in range(warmup):
+            ctx.matvec(prec, x, out)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(steps):
+            ctx.matvec(prec, x, out)
+        torch.cuda.synchronize()
+        return 1e3 * (time.perf_counter() - t) / steps
+
+    out = {"workload": "line_bundle over silicon (200 um, eps_r 11.9, 10 S/m) on PEC", "aim_grid": list(grid),
+           "freq_hz": freq, "n_e": lay.n_e, "n_t": lay.n_t, "z_interface_below_grid_m": 1e-6,
+           "free_space_product_ms": {"mixed": product_ms(slim.SLIM_MIXED, y), "fp64": product_ms(slim.SLIM_FP64, y64)}}
     z_if = lay.grid_origin[2] - 1e-6
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ctx.set_medium(z_if, [(200e-6, 11.9, 10.0)], "pec")
-    t_kern = time.perf_counter() - t0
+    out["medium_build_s"] = time.perf_counter() - t0
+    pm, pd = product_ms(slim.SLIM_MIXED, y), product_ms(slim.SLIM_FP64, y64)
+    out["layered_product_ms"] = {"mixed": pm, "fp64": pd}
+    out["layered_matvecs_per_s"] = {"mixed": 1e3 / pm, "fp64": 1e3 / pd}
+    ne = lay.n_e
+    ym, yd = y.cpu().numpy(), y64.cpu().numpy()
+    out["layered_mixed_vs_fp64_rel_err"] = {
+        "y1": float(np.linalg.norm(ym[:ne] - yd[:ne]) / np.linalg.norm(yd[:ne])),
+        "y2": float(np.linalg.norm(ym[ne:] - yd[ne:]) / np.linalg.norm(yd[ne:]))}
     n3 = grid[0] * grid[1] * grid[2]
     src = torch.tensor(random_complex(4 * n3, 5), dtype=torch.complex128, device="cuda")
     dst = torch.zeros_like(src)
-    out = {"workload": "line_bundle over silicon (200 um, eps_r 11.9, 10 S/m) on PEC", "aim_grid": list(grid),
-           "freq_hz": freq, "z_interface_below_grid_m": 1e-6, "kernel_build_s": t_kern}
     for name, prec in (("mixed", slim.SLIM_MIXED), ("fp64", slim.SLIM_FP64)):
         res = {}
         for kind, call in (("layered", lambda: ctx.aim_convolve_layered(prec, src, dst)),
@@ -265,8 +291,8 @@ def layered_study(steps=10, warmup=2):
         b = layered_bytes(grid, prec == slim.SLIM_MIXED)
         res["layered_algorithmic_bytes"] = b
         res["layered_hbm_frac"] = b / (res["layered_ms"] * 1e-3) / HBM_PEAK
-        out[name] = res
-    log("layered convolution study: %s" % out)
+        out["convolution_" + name] = res
+    log("layered study: %s" % out)
     ctx.close()
     torch.cuda.empty_cache()
     return out
@@ -288,9 +314,9 @@ def main():
     ap.add_argument("--no-sched-study", action="store_true",
                     help="skip the makespan study (naive / LPT / trained cost model)")
     ap.add_argument("--no-layered", action="store_true",
-                    help="skip the layered-medium convolution study (bundle over a silicon substrate)")
+                    help="skip the layered-medium study (bundle over a silicon substrate)")
     ap.add_argument("--layered-only", action="store_true",
-                    help="only run the layered-medium convolution study and print its JSON")
+                    help="only run the layered-medium study and print its JSON")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the product is built and applied on a single MI355X "
@@ -310,7 +336,7 @@ def main():
     from inputs.geometry import random_complex
 
     if args.layered_only:
-        print(json.dumps({"layered_convolution": layered_study(args.steps, args.warmup)}), flush=True)
+        print(json.dumps({"layered_substrate": layered_study(args.steps, args.warmup)}), flush=True)
         return
     kw, freq, grid = WORKLOADS[args.workload]
     t0 = time.time()
@@ -415,7 +441,7 @@ def main():
     if not args.no_layered:
         ctx.close()       # frees the device arenas of this workload first
         torch.cuda.empty_cache()
-        result["layered_convolution"] = layered_study()
+        result["layered_substrate"] = layered_study()
     if not args.no_cpu_baseline:
         t0 = time.time()
         result["cpu_baseline"] = cpu_baseline(mesh, lay, freq, grid)

@@ -33,6 +33,7 @@
 //     their axis, the index of z + z' unwrapped) and transformed.  The spectrum
 //     is kept for kx <= Nx, ky <= Ny and all 2Nz values of kz.
 #include <algorithm>
+#include <cstdio>
 
 #include "ctx.hpp"
 
@@ -614,6 +615,10 @@ void build_layered(Ctx& c, const slim_medium& md, hipStream_t s) {
     SLIM_HIP(hipStreamSynchronize(s));
   }
   c.d_lay.alloc(size_t(4 * full) * 16);
+  if (c.opts.verbose) {
+    std::fprintf(stderr, "[slim medium] reflected grid kernels and spectra done (%d path nodes)\n", n_nodes);
+    std::fflush(stderr);
+  }
   // ---- near field: exact reflected part minus its grid part, on the existing CSRs ----
   if (c.nnz_A + c.nnz_P > 0) {
     // table of the integrated remainders over the grid's (rho, zeta) range
@@ -674,8 +679,23 @@ void build_layered(Ctx& c, const slim_medium& md, hipStream_t s) {
       nr_.lim[0] = d2(lim.cxx); nr_.lim[1] = d2(lim.czz); nr_.lim[2] = d2(lim.cphi); nr_.lim[3] = d2(lim.czx);
       nr_.rwg = rwg ? 1 : 0;
       nr_.vals = v128.as<double2>();
-      hipLaunchKernelGGL(k_near_refl, dim3(nblk(nnz)), dim3(256), 0, s, nr_);
-      SLIM_HIP(hipGetLastError());
+      // chunks of 2^22 entries, so that a verbose build reports progress
+      const int64_t chunk = int64_t(1) << 22;
+      for (int64_t k0c = 0; k0c < nnz; k0c += chunk) {
+        NearRefl part = nr_;
+        part.rows = nr_.rows + k0c;
+        part.cols = nr_.cols + k0c;
+        part.vals = nr_.vals + k0c;
+        part.nnz = std::min(chunk, nnz - k0c);
+        hipLaunchKernelGGL(k_near_refl, dim3(nblk(part.nnz)), dim3(256), 0, s, part);
+        SLIM_HIP(hipGetLastError());
+        if (c.opts.verbose && (k0c / chunk) % 4 == 3) {
+          SLIM_HIP(hipStreamSynchronize(s));
+          std::fprintf(stderr, "[slim medium] reflected near field %s: %lld / %lld\n", rwg ? "L_A" : "L_phi",
+                       (long long)(k0c + part.nnz), (long long)nnz);
+          std::fflush(stderr);
+        }
+      }
       hipLaunchKernelGGL(k_c128_to_c64_n, dim3(nblk(nnz)), dim3(256), 0, s, v128.as<double2>(), v64.as<float2>(), nnz);
       SLIM_HIP(hipGetLastError());
       SLIM_HIP(hipStreamSynchronize(s));
