@@ -167,34 +167,61 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_pass(PassArgs a) {
   C2<T>* out = reinterpret_cast<C2<T>*>(a.out) + blockIdx.z * a.comp_out;
   const int g1 = blockIdx.x * W;     // first line along o1
   const int o2 = blockIdx.y;
-  // load
-  for (int e = threadIdx.x; e < ELEMS; e += kFftThreads) {
-    int b, i;
+  // Each thread owns PER elements of the batch.  All of its global loads are issued
+  // before any is used (registers first, then LDS), so that PER requests per lane are
+  // in flight instead of one.
+  constexpr int PER = ELEMS / kFftThreads;
+  static_assert(ELEMS % kFftThreads == 0, "batch not a multiple of the workgroup");
+  auto coords = [&](int p, int& b, int& i) {
+    const int e = threadIdx.x + p * kFftThreads;
     if (CONTIG) { b = e / L; i = e % L; } else { b = e % W; i = e / W; }
-    const int o1 = g1 + b;
-    C2<T> v = {T(0), T(0)};
-    if (o1 < a.n1 && i < a.n_in) v = ld_stream(in + (o1 * a.in_o1 + o2 * a.in_o2 + int64_t(i) * a.in_e));
-    lds[pidx<L>(b, i)] = v;
+  };
+  {
+    C2<T> v[PER];
+#pragma unroll
+    for (int p = 0; p < PER; ++p) {
+      int b, i;
+      coords(p, b, i);
+      const int o1 = g1 + b;
+      v[p] = {T(0), T(0)};
+      if (o1 < a.n1 && i < a.n_in) v[p] = ld_stream(in + (o1 * a.in_o1 + o2 * a.in_o2 + int64_t(i) * a.in_e));
+    }
+#pragma unroll
+    for (int p = 0; p < PER; ++p) {
+      int b, i;
+      coords(p, b, i);
+      lds[pidx<L>(b, i)] = v[p];
+    }
   }
   __syncthreads();
   if (MODE == 1) fft_batch<T, L, ELEMS, true>(lds, tw);
   else fft_batch<T, L, ELEMS, false>(lds, tw);
   if (MODE == 2) {
     const C2<T>* G = reinterpret_cast<const C2<T>*>(a.mul);
-    for (int e = threadIdx.x; e < ELEMS; e += kFftThreads) {
+    C2<T> gv[PER];
+#pragma unroll
+    for (int p = 0; p < PER; ++p) {
       int b, i;
-      if (CONTIG) { b = e / L; i = e % L; } else { b = e % W; i = e / W; }
+      coords(p, b, i);
       const int o1 = g1 + b;
       const int m1 = o1 <= a.h_o1 ? o1 : 2 * a.h_o1 - o1, m2 = o2 <= a.h_o2 ? o2 : 2 * a.h_o2 - o2,
                 me = i <= a.h_e ? i : 2 * a.h_e - i;
-      if (o1 < a.n1) lds[pidx<L>(b, i)] = cmul(lds[pidx<L>(b, i)], G[m1 * a.mul_o1 + m2 * a.mul_o2 + int64_t(me) * a.mul_e]);
+      gv[p] = {T(0), T(0)};
+      if (o1 < a.n1) gv[p] = G[m1 * a.mul_o1 + m2 * a.mul_o2 + int64_t(me) * a.mul_e];
+    }
+#pragma unroll
+    for (int p = 0; p < PER; ++p) {
+      int b, i;
+      coords(p, b, i);
+      if (g1 + b < a.n1) lds[pidx<L>(b, i)] = cmul(lds[pidx<L>(b, i)], gv[p]);
     }
     __syncthreads();
     fft_batch<T, L, ELEMS, true>(lds, tw);
   }
-  for (int e = threadIdx.x; e < ELEMS; e += kFftThreads) {
+#pragma unroll
+  for (int p = 0; p < PER; ++p) {
     int b, i;
-    if (CONTIG) { b = e / L; i = e % L; } else { b = e % W; i = e / W; }
+    coords(p, b, i);
     const int o1 = g1 + b;
     if (o1 < a.n1 && i < a.n_out) st_stream(out + (o1 * a.out_o1 + o2 * a.out_o2 + int64_t(i) * a.out_e), lds[pidx<L>(b, i)]);
   }
