@@ -259,6 +259,13 @@ typedef struct slim_medium {
  *   2 (origin_z - z_interface) + s h_z; the last two axes are |offset| in
  *   nodes. */
 slim_status slim_set_medium(slim_ctx* ctx, const slim_medium* medium);
+/* slim_layered_gammas (host only, no device): the TM and TE voltage reflection
+ * coefficients Gamma_e, Gamma_h of the medium seen from air at the interface, at
+ * frequency freq (Hz), for n complex transverse wavenumbers on or above the real
+ * axis.  These are the coefficients the reflected kernels are built from.
+ * kr: 2n doubles (re, im); out: 4n doubles (Gamma_e re, im, Gamma_h re, im per
+ * point).  SLIM_E_ARG on bad layer data or null pointers. */
+slim_status slim_layered_gammas(const slim_medium* medium, double freq, int64_t n, const double* kr, double* out);
 slim_status slim_aim_convolve_layered(slim_ctx* ctx, slim_prec prec, const void* src_dev, void* dst_dev, void* stream);
 slim_status slim_get_layered_kernels(const slim_ctx* ctx, double* out);
 slim_status slim_get_near(const slim_ctx* ctx, int32_t which, int64_t* ptr, int32_t* col, double* val);

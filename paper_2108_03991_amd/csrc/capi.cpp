@@ -374,6 +374,18 @@ slim_status slim_aim_convolve_layered(slim_ctx* h, slim_prec prec, const void* s
   });
 }
 
+slim_status slim_layered_gammas(const slim_medium* m, double freq, int64_t n, const double* kr, double* out) {
+  if (!m) return SLIM_E_ARG;
+  try {
+    layered_gammas(*m, freq, n, kr, out);
+    return SLIM_OK;
+  } catch (const Error& e) {
+    return e.code;
+  } catch (...) {
+    return SLIM_E_ARG;
+  }
+}
+
 slim_status slim_get_layered_kernels(const slim_ctx* h, double* out) {
   if (!h) return SLIM_E_ARG;
   if (!h->c.layered) return SLIM_E_STATE;

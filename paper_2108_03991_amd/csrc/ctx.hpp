@@ -174,6 +174,7 @@ void aim_convolve(Ctx& c, bool fp64, int ncomp, hipStream_t s, int comp0 = 0, bo
 void aim_convolve_layered(Ctx& c, bool fp64, hipStream_t s);   // oct_in -> oct_out, 4 components
 // layered.hip
 void build_layered(Ctx& c, const slim_medium& m, hipStream_t s);
+void layered_gammas(const slim_medium& m, double freq, int64_t n, const double* kr, double* out);   // host only
 // sched.cpp
 void pack_tiles(Ctx& c, int mode);
 // precond.hip

@@ -534,6 +534,37 @@ __global__ void k_c128_to_c64_n(const double2* in, float2* out, int64_t n) {
 
 }  // namespace
 
+void layered_gammas(const slim_medium& md, double freq, int64_t n, const double* kr, double* out) {
+  SLIM_REQUIRE(std::isfinite(freq) && freq > 0, SLIM_E_ARG, "frequency must be positive");
+  SLIM_REQUIRE(n >= 0 && (n == 0 || (kr && out)), SLIM_E_ARG, "bad arguments");
+  SLIM_REQUIRE(md.n_layers >= 0 && (md.n_layers == 0 || md.layers), SLIM_E_ARG, "bad layer list");
+  Stack st;
+  for (int l = 0; l < md.n_layers; ++l) {
+    const slim_layer& L = md.layers[l];
+    SLIM_REQUIRE(std::isfinite(L.thickness) && L.thickness > 0 && std::isfinite(L.eps_r) && L.eps_r > 0 &&
+                     std::isfinite(L.sigma) && L.sigma >= 0,
+                 SLIM_E_ARG, "layer " + std::to_string(l) + ": thickness > 0, eps_r > 0, sigma >= 0");
+    st.layers.push_back(L);
+  }
+  st.pec = md.bottom_pec != 0;
+  if (!st.pec) {
+    SLIM_REQUIRE(std::isfinite(md.bottom_eps_r) && md.bottom_eps_r > 0 && std::isfinite(md.bottom_sigma) &&
+                     md.bottom_sigma >= 0,
+                 SLIM_E_ARG, "bottom half-space: eps_r > 0, sigma >= 0");
+    st.eb = md.bottom_eps_r;
+    st.sb = md.bottom_sigma;
+  }
+  const double w = 2.0 * kPi * freq;
+  for (int64_t i = 0; i < n; ++i) {
+    cd ge, gh;
+    reflection(st, w, cd(kr[2 * i], kr[2 * i + 1]), ge, gh);
+    out[4 * i] = ge.real();
+    out[4 * i + 1] = ge.imag();
+    out[4 * i + 2] = gh.real();
+    out[4 * i + 3] = gh.imag();
+  }
+}
+
 void build_layered(Ctx& c, const slim_medium& md, hipStream_t s) {
   SLIM_REQUIRE(c.built && !c.plain, SLIM_E_STATE, "no AIM operator built");
   SLIM_REQUIRE(md.n_layers >= 0 && (md.n_layers == 0 || md.layers), SLIM_E_ARG, "bad layer list");

@@ -118,6 +118,7 @@ def lib():
         L.slim_set_medium.argtypes = [vp, C.POINTER(Medium)]
         L.slim_aim_convolve_layered.argtypes = [vp, i32, vp, vp, vp]
         L.slim_get_layered_kernels.argtypes = [vp, dp]
+        L.slim_layered_gammas.argtypes = [C.POINTER(Medium), C.c_double, i64, dp, dp]
         L.slim_profile.argtypes = [vp, i32]
         L.slim_profile_read.argtypes = [vp, dp, C.POINTER(i64)]
         for name in ("slim_create", "slim_set_mesh", "slim_set_materials", "slim_build", "slim_get_layout",
@@ -126,7 +127,7 @@ def lib():
                      "slim_sched_train", "slim_sched_set_mode", "slim_mlp_forward_backward", "slim_profile",
                      "slim_profile_read", "slim_aim_convolve", "slim_get_aim", "slim_get_near",
                      "slim_precond_apply", "slim_get_precond", "slim_precond_partition", "slim_set_medium",
-                     "slim_aim_convolve_layered", "slim_get_layered_kernels"):
+                     "slim_aim_convolve_layered", "slim_get_layered_kernels", "slim_layered_gammas"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -138,7 +139,7 @@ EXPORTS = ["slim_default_build_opts", "slim_create", "slim_destroy", "slim_last_
            "slim_sched_tiles", "slim_sched_train", "slim_sched_set_mode", "slim_mlp_forward_backward",
            "slim_profile", "slim_profile_read", "slim_aim_convolve", "slim_get_aim", "slim_get_near",
            "slim_precond_apply", "slim_get_precond", "slim_precond_partition", "slim_set_medium",
-           "slim_aim_convolve_layered", "slim_get_layered_kernels"]
+           "slim_aim_convolve_layered", "slim_get_layered_kernels", "slim_layered_gammas"]
 
 
 def _ptr(t):
@@ -164,6 +165,38 @@ def default_build_opts(**kw):
         else:
             setattr(o, k, v)
     return o
+
+
+def _medium(z_interface, layers, bottom):
+    """slim_medium for (layers top-down as (thickness, eps_r, sigma), bottom "pec" or (eps_r, sigma));
+    returns the struct and the layer array it points to (keep both alive for the call)."""
+    arr = (Layer * max(1, len(layers)))(*[Layer(*map(float, l)) for l in layers])
+    m = Medium()
+    m.z_interface = float(z_interface)
+    m.n_layers = len(layers)
+    m.layers = C.cast(arr, C.POINTER(Layer))
+    if isinstance(bottom, str):
+        if bottom != "pec":
+            raise ValueError("bottom must be 'pec' or (eps_r, sigma)")
+        m.bottom_pec = 1
+    else:
+        m.bottom_pec = 0
+        m.bottom_eps_r, m.bottom_sigma = (float(v) for v in bottom)
+    return m, arr
+
+
+def layered_gammas(layers, bottom, freq, kr):
+    """Host-only: (Gamma_e, Gamma_h) of the stack at complex transverse wavenumbers kr."""
+    m, keep = _medium(0.0, layers, bottom)
+    kr = np.ascontiguousarray(np.asarray(kr, dtype=np.complex128))
+    out = np.zeros(4 * kr.size)
+    st = lib().slim_layered_gammas(C.byref(m), float(freq), kr.size,
+                                   kr.view(np.float64).ctypes.data_as(C.POINTER(C.c_double)),
+                                   out.ctypes.data_as(C.POINTER(C.c_double)))
+    if st != 0:
+        raise SlimError(st, "slim_layered_gammas failed")
+    o = out.view(np.complex128).reshape(-1, 2)
+    return o[:, 0].copy(), o[:, 1].copy()
 
 
 class Context:
@@ -267,18 +300,7 @@ class Context:
 
     def set_medium(self, z_interface, layers=(), bottom="pec"):
         """Layered background: layers top-down as (thickness, eps_r, sigma); bottom "pec" or (eps_r, sigma)."""
-        arr = (Layer * max(1, len(layers)))(*[Layer(*map(float, l)) for l in layers])
-        m = Medium()
-        m.z_interface = float(z_interface)
-        m.n_layers = len(layers)
-        m.layers = C.cast(arr, C.POINTER(Layer))
-        if isinstance(bottom, str):
-            if bottom != "pec":
-                raise ValueError("bottom must be 'pec' or (eps_r, sigma)")
-            m.bottom_pec = 1
-        else:
-            m.bottom_pec = 0
-            m.bottom_eps_r, m.bottom_sigma = (float(v) for v in bottom)
+        m, keep = _medium(z_interface, layers, bottom)
         self._check(lib().slim_set_medium(self._h, C.byref(m)))
 
     def aim_convolve_layered(self, prec, src, dst, stream=None):

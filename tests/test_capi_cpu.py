@@ -66,3 +66,23 @@ def test_precond_partition_matches_oracle(cap, overlap):
         assert len(got) == len(ref)
         for (ext, pos), b in zip(got, ref):
             assert np.array_equal(ext, b.ext) and np.array_equal(pos, b.own_pos)
+
+
+def test_layered_gammas_match_oracle():
+    """Host-only: the library's generalized-reflection recursion against the oracle's
+    impedance recursion, for several stacks, on the real axis and above it."""
+    from oracle import mgf
+    from paper_2108_03991_amd import slim
+    stacks = [([(200e-6, 11.9, 10.0)], "pec"), ([(30e-6, 4.0, 0.0), (495e-6, 11.9, 10.0)], "pec"),
+              ([], (11.9, 10.0)), ([(3e-6, 4.0, 0.0)], (2.0, 0.5)), ([], "pec")]
+    for f in (1e9, 20e9):
+        k0 = 2 * np.pi * f / mgf.C0
+        kr = np.concatenate([np.linspace(0.01, 3e3, 57) + 0j,
+                             np.linspace(1.0, 5e2, 23) + 1j * np.linspace(10.0, 80.0, 23),
+                             np.array([0.999 * k0, 1.001 * k0, 1e6, 3e7]) + 0j])
+        for layers, bottom in stacks:
+            ge, gh = slim.layered_gammas(layers, bottom, f, kr)
+            ref_e, ref_h = mgf.gammas(mgf.Stack(layers, bottom), f, kr)
+            assert np.abs(ge - ref_e).max() <= 1e-12 and np.abs(gh - ref_h).max() <= 1e-12, (layers, bottom, f)
+    with pytest.raises(slim.SlimError):
+        slim.layered_gammas([(-1.0, 4.0, 0.0)], "pec", 1e9, kr)
