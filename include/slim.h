@@ -241,7 +241,9 @@ typedef struct slim_medium {
  *   SLIM_E_ARG: bad layer data, or the grid reaches the interface.
  *   SLIM_E_UNSUPPORTED: the grid is too large electrically for the
  *   quadrature path.
- * Replaces any earlier medium.
+ * Replaces any earlier medium.  A STATE or ARG error leaves the context
+ * unchanged.  A later failure (UNSUPPORTED, OOM, HIP) leaves it without a
+ * medium, with its free-space near field.
  *
  * slim_aim_convolve_layered: the four grid components (x, y, z current and
  *   charge; 4 x Nx Ny Nz complex128 device arrays, node order x fastest),

@@ -565,6 +565,9 @@ void layered_gammas(const slim_medium& md, double freq, int64_t n, const double*
   }
 }
 
+static void build_layered_device(Ctx& c, const slim_medium& md, const Stack& st, double d_min, double z0, hipStream_t s);
+static void restore_free_near(Ctx& c);
+
 void build_layered(Ctx& c, const slim_medium& md, hipStream_t s) {
   SLIM_REQUIRE(c.built && !c.plain, SLIM_E_STATE, "no AIM operator built");
   SLIM_REQUIRE(md.n_layers >= 0 && (md.n_layers == 0 || md.layers), SLIM_E_ARG, "bad layer list");
@@ -586,14 +589,40 @@ void build_layered(Ctx& c, const slim_medium& md, hipStream_t s) {
     st.eb = md.bottom_eps_r;
     st.sb = md.bottom_sigma;
   }
-  const GridDef& G = c.grid;
-  const double z0 = G.origin[2] - md.z_interface;
+  const double z0 = c.grid.origin[2] - md.z_interface;
   SLIM_REQUIRE(std::isfinite(md.z_interface) && z0 > 0.0, SLIM_E_ARG,
                "the AIM grid reaches the interface: its lowest node must lie above z_interface");
-  const int Nx = G.N[0], Ny = G.N[1], Nz = G.N[2];
-  const double w = c.omega, k0 = c.k0;
   c.layered = false;
   c.drop_graphs();   // captured products hold the free-space convolution
+  try {
+    build_layered_device(c, md, st, d_min, z0, s);
+  } catch (...) {
+    // a device failure leaves the context without a medium, with its free-space near field
+    restore_free_near(c);
+    throw;
+  }
+  c.layered = true;
+  c.lay_zif = md.z_interface;
+}
+
+static void restore_free_near(Ctx& c) {
+  for (int which = 0; which < 2; ++which) {
+    DevBuf& fr = which == 0 ? c.d_nA_free : c.d_nP_free;
+    DevBuf& v128 = which == 0 ? c.d_nA_v128 : c.d_nP_v128;
+    DevBuf& v64 = which == 0 ? c.d_nA_v64 : c.d_nP_v64;
+    const int64_t nnz = which == 0 ? c.nnz_A : c.nnz_P;
+    if (!fr.p || nnz == 0) continue;
+    if (hipMemcpy(v128.p, fr.p, v128.bytes, hipMemcpyDeviceToDevice) != hipSuccess) continue;
+    hipLaunchKernelGGL(k_c128_to_c64_n, dim3(nblk(nnz)), dim3(256), 0, 0, v128.as<double2>(), v64.as<float2>(), nnz);
+    (void)hipDeviceSynchronize();
+  }
+}
+
+static void build_layered_device(Ctx& c, const slim_medium& md, const Stack& st, double d_min, double z0,
+                                 hipStream_t s) {
+  const GridDef& G = c.grid;
+  const int Nx = G.N[0], Ny = G.N[1], Nz = G.N[2];
+  const double w = c.omega, k0 = c.k0;
   // ---- large-k_rho limits: the medium right below the interface seen as a half-space ----
   cd ge_inf, gh_inf;
   if (st.layers.empty() && st.pec) {
@@ -733,8 +762,6 @@ void build_layered(Ctx& c, const slim_medium& md, hipStream_t s) {
     }
   }
   SLIM_HIP(hipStreamSynchronize(s));
-  c.layered = true;
-  c.lay_zif = md.z_interface;
   c.lay_nodes = n_nodes;
 }
 
