@@ -64,8 +64,8 @@ typedef enum {
  *            (a 48-bit significand, the same bytes as complex128), grids,
  *            near field and vectors complex128.
  * SLIM_MIXED: internal blocks from the hi complex64 part with FP32
- *            accumulation (or split-BF16 MFMA, see internal_kernel), complex64
- *            FFT convolution and near field, FP32 stencil weights.          */
+ *            accumulation, complex64 FFT convolution and near field, FP32
+ *            stencil weights.                                                */
 typedef enum { SLIM_FP64 = 0, SLIM_MIXED = 1 } slim_prec;
 
 typedef struct {
@@ -86,7 +86,8 @@ typedef struct {
   double q, c_near;
   int32_t sched_mode;     /* 0 = LPT on flop counts, 1 = MLP cost model, 2 = naive */
   int32_t tile_rows;      /* row-panel height of internal tiles (0 = autotune)     */
-  int32_t internal_kernel;/* mixed internal GEMV: 0 = FP32 FMA, 1 = split-BF16 MFMA */
+  int32_t internal_kernel;/* mixed internal GEMV: 0 = FP32 FMA (the only one built;
+                             any other value is SLIM_E_UNSUPPORTED)                 */
   int32_t slots;          /* persistent workgroups of the internal kernel (0 = auto) */
   int64_t mem_budget;     /* bytes of device memory the build may use (0 = no cap)  */
   int32_t verbose;

@@ -309,6 +309,9 @@ void build_all(Ctx& c, const slim_build_opts& o) {
   for (int k = 0; aim && k < 3; ++k)
     SLIM_REQUIRE(o.grid[k] >= 8 && o.grid[k] <= 512 && (o.grid[k] & (o.grid[k] - 1)) == 0, SLIM_E_UNSUPPORTED,
                  "AIM grid size must be a power of two between 8 and 512 per axis");
+  SLIM_REQUIRE(o.internal_kernel == 0, SLIM_E_UNSUPPORTED,
+               "internal_kernel: only the FP32-FMA GEMV (0) is built; a split-BF16 MFMA kernel would read the same "
+               "bytes at one right-hand side");
   SLIM_HIP(hipSetDevice(c.device));
   c.built = false;
   c.opts = o;

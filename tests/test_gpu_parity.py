@@ -161,6 +161,9 @@ def test_mesh_and_state_errors(c1_mesh):
         ctx.build(freq=10e9, grid=(12, 12, 12))       # the FFT needs 2N a power of two
     assert ei.value.code == 8
     with pytest.raises(slim.SlimError) as ei:
+        ctx.build(freq=10e9, internal_kernel=1)       # only the FP32-FMA internal GEMV is built
+    assert ei.value.code == 8
+    with pytest.raises(slim.SlimError) as ei:
         ctx.build(freq=10e9, mem_budget=1000)
     assert ei.value.code == 4
 
