@@ -78,6 +78,17 @@ def substrate_c4():
     return Stack(layers=[(200e-6, 11.9, 10.0)], bottom="pec", z_if=0.0)
 
 
+def table1_bus():
+    """The high-speed-bus stack of Table I: oxide 30 um (eps_r 4), silicon 495 um (eps_r 11.9,
+    10 S/m), PEC."""
+    return Stack(layers=[(30e-6, 4.0, 0.0), (495e-6, 11.9, 10.0)], bottom="pec", z_if=0.0)
+
+
+def table1_interposer():
+    """The fan-out-interposer stack of Table I: oxide 27.5 um, silicon 497.5 um (same materials), PEC."""
+    return Stack(layers=[(27.5e-6, 4.0, 0.0), (497.5e-6, 11.9, 10.0)], bottom="pec", z_if=0.0)
+
+
 def _kz(k2, krho):
     """k_z = sqrt(k^2 - k_rho^2) on the branch Im k_z <= 0 (k_rho on or above the real axis)."""
     return -1j * np.sqrt(krho * krho - k2 + 0j)

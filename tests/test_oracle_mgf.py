@@ -101,14 +101,26 @@ def test_thick_lossy_slab_equals_half_space():
         np.testing.assert_allclose(a[key], b[key], rtol=1e-9, atol=1e-9 * np.abs(a["phi"]).max())
 
 
-def test_lossy_stack_is_passive():
+@pytest.mark.parametrize("stack", [mgf.substrate_c4, mgf.table1_bus, mgf.table1_interposer])
+def test_lossy_stack_is_passive(stack):
     """For propagating waves (k_rho < k0) a lossy passive stack reflects at most what comes in."""
-    st = mgf.substrate_c4()
+    st = stack()
     for f in (1e8, 1e9, 1e10):
         k0 = 2 * np.pi * f / mgf.C0
         kr = np.linspace(0.0, 0.999 * k0, 200) + 0j
         ge, gh = mgf.gammas(st, f, kr)
         assert np.all(np.abs(ge) < 1.0) and np.all(np.abs(gh) < 1.0)
+
+
+def test_two_layer_stack_reduces_to_one_layer():
+    """A 'two-layer' stack whose layers are the same material equals one layer of the summed
+    thickness (TL recursion through an interface with no contrast)."""
+    f = 5e9
+    a = mgf.Stack([(100e-6, 11.9, 10.0), (100e-6, 11.9, 10.0)], "pec")
+    b = mgf.substrate_c4()
+    kr = np.concatenate([np.linspace(0.1, 3e3, 60) + 0j, np.linspace(1.0, 300.0, 20) + 30j])
+    for x, y in zip(mgf.gammas(a, f, kr), mgf.gammas(b, f, kr)):
+        np.testing.assert_allclose(x, y, rtol=1e-12, atol=1e-14)
 
 
 def _d(fun, x, h):
@@ -118,10 +130,10 @@ def _d(fun, x, h):
     return (4 * d1 - d2) / 3
 
 
-@pytest.mark.parametrize("freq", [1e9, 20e9])
-def test_mixed_potential_field_equals_tl_field(freq):
+@pytest.mark.parametrize("freq,stack", [(1e9, mgf.substrate_c4), (20e9, mgf.substrate_c4), (5e9, mgf.table1_bus)])
+def test_mixed_potential_field_equals_tl_field(freq, stack):
     """E of x- and z-directed unit current elements: mixed potentials vs TL voltages/currents."""
-    st = mgf.substrate_c4()
+    st = stack()
     w = 2 * np.pi * freq
     k0 = w / mgf.C0
     eps0, mu0 = mgf.EPS0, mgf.MU0
