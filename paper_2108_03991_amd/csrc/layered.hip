@@ -300,6 +300,8 @@ std::vector<cd> node_table(const Stack& st, double w, double k0, double rho_max,
                "layered kernels: the grid spans too many substrate wavelengths for the quadrature path");
   const double k_end = a + 40.0 / zmin;
   const double dk_max = std::min(0.5 * kPi / rho_max, 0.25 / zmin);
+  SLIM_REQUIRE(zmin > 0.0 && (k_end - a) / dk_max <= 5.0e5, SLIM_E_UNSUPPORTED,
+               "layered kernels: the interface gap is too small against the grid extent (more than 4M path nodes)");
   std::vector<double> gx, gw;
   gauss_legendre(8, gx, gw);
   std::vector<cd> kr, wk;
@@ -687,7 +689,9 @@ static void build_layered_device(Ctx& c, const slim_medium& md, const Stack& st,
     double kmax = k0;
     for (const slim_layer& Ly : st.layers) kmax = std::max(kmax, std::abs(w * std::sqrt(kMu0 * eps_c(w, Ly.eps_r, Ly.sigma))));
     dlt = std::min(dlt, 0.3 / kmax);
-    dlt = std::max({dlt, rho_max / 2000.0, (zhi - zlo) / 2000.0});
+    SLIM_REQUIRE(rho_max / dlt <= 4000.0 && (zhi - zlo) / dlt <= 4000.0, SLIM_E_UNSUPPORTED,
+                 "layered near field: the grid spans more than 4000 table steps (the step is the smaller of the "
+                 "gap between the lowest grid plane and the interface and 1/16 of the thinnest layer)");
     const int nr = int(std::ceil(rho_max / dlt)) + 3, nz = int(std::ceil((zhi - zlo) / dlt)) + 4;
     const double tz0 = zlo - dlt;
     std::vector<cd> tab2 = node_table(st, w, k0, (nr - 1) * dlt, tz0, lim);
