@@ -241,7 +241,9 @@ typedef struct slim_medium {
  *   SLIM_E_STATE: no AIM operator built.
  *   SLIM_E_ARG: bad layer data, or the grid reaches the interface.
  *   SLIM_E_UNSUPPORTED: the grid is too large electrically for the
- *   quadrature path.
+ *   quadrature path, or too large against the gap between its lowest plane
+ *   and the interface (more than 4M path nodes or 4000 near-field table
+ *   steps per axis).
  * Replaces any earlier medium.  A STATE or ARG error leaves the context
  * unchanged.  A later failure (UNSUPPORTED, OOM, HIP) leaves it without a
  * medium, with its free-space near field.
