@@ -74,16 +74,25 @@ def test_reflected_entries_pec_images(two_boxes):
     np.testing.assert_allclose(aim.reflected_phi_entries(g, FREQ, st, t, u), ref_p, rtol=1e-11)
 
 
-def test_reflected_operators_are_reciprocal(two_boxes):
+@pytest.fixture(scope="module")
+def reflected_dense(two_boxes):
+    """Reflected L_A and L_phi over the lossy substrate on every pair (computed once)."""
     g, grid = two_boxes
     st = mgf.substrate_c4()
     st.z_if = grid.origin[2] - 1 * UM
     m, n = np.meshgrid(np.arange(g.n_e), np.arange(g.n_e), indexing='ij')
     LA = aim.reflected_entries(g, FREQ, st, m.ravel(), n.ravel()).reshape(g.n_e, g.n_e)
-    np.testing.assert_allclose(LA, LA.T, rtol=0, atol=1e-10 * np.abs(LA).max())
-    assert np.abs(LA).max() > 0
     t, u = np.meshgrid(np.arange(g.n_t), np.arange(g.n_t), indexing='ij')
     LP = aim.reflected_phi_entries(g, FREQ, st, t.ravel(), u.ravel()).reshape(g.n_t, g.n_t)
+    return st, LA, LP
+
+
+def test_reflected_operators_are_reciprocal(two_boxes, reflected_dense):
+    g, grid = two_boxes
+    st, LA, LP = reflected_dense
+    m, n = np.meshgrid(np.arange(g.n_e), np.arange(g.n_e), indexing='ij')
+    np.testing.assert_allclose(LA, LA.T, rtol=0, atol=1e-10 * np.abs(LA).max())
+    assert np.abs(LA).max() > 0
     np.testing.assert_allclose(LP, LP.T, rtol=0, atol=1e-10 * np.abs(LP).max())
     # the reflected grid part is symmetric too
     cE, wE, cT, wT = aim.stencil_weights(grid, g)
@@ -92,19 +101,16 @@ def test_reflected_operators_are_reciprocal(two_boxes):
     np.testing.assert_allclose(GA, GA.T, rtol=0, atol=1e-10 * np.abs(GA).max())
 
 
-def test_layered_aim_matches_dense_layered_operator(two_boxes):
+def test_layered_aim_matches_dense_layered_operator(two_boxes, reflected_dense):
     """Far pairs: AIM approximation of the total kernel; near pairs: exact.  Agreement to AIM accuracy."""
     g, grid = two_boxes
-    st = mgf.substrate_c4()
-    st.z_if = grid.origin[2] - 1 * UM
+    st, LAr, LPr = reflected_dense
     k0 = 2 * np.pi * FREQ / mgf.C0
     op = aim.build_aim_layered(g, grid, FREQ, st)
     m, n = np.meshgrid(np.arange(g.n_e), np.arange(g.n_e), indexing='ij')
-    LA = (aim.exact_entries(g, k0, m.ravel(), n.ravel())
-          + aim.reflected_entries(g, FREQ, st, m.ravel(), n.ravel())).reshape(g.n_e, g.n_e)
+    LA = aim.exact_entries(g, k0, m.ravel(), n.ravel()).reshape(g.n_e, g.n_e) + LAr
     t, u = np.meshgrid(np.arange(g.n_t), np.arange(g.n_t), indexing='ij')
-    LP = (aim.exact_phi_entries(g, k0, t.ravel(), u.ravel())
-          + aim.reflected_phi_entries(g, FREQ, st, t.ravel(), u.ravel())).reshape(g.n_t, g.n_t)
+    LP = aim.exact_phi_entries(g, k0, t.ravel(), u.ravel()).reshape(g.n_t, g.n_t) + LPr
     rng = np.random.default_rng(2)
     j = rng.standard_normal(g.n_e) + 1j * rng.standard_normal(g.n_e)
     q = rng.standard_normal(g.n_t) + 1j * rng.standard_normal(g.n_t)
