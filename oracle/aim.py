@@ -330,11 +330,11 @@ def _tri_rule(g: RWG, order=REFL_ORDER):
     return tri_points(Vt, order)          # (N_T, q, 3), (N_T, q) with weights summing to A_t
 
 
-def _reflected_pair_integrals(g: RWG, freq, stack, T, U):
-    """For triangle pairs (T[b], U[b]), TRI(2) x TRI(2):
+def _reflected_pair_integrals(g: RWG, freq, stack, T, U, order=REFL_ORDER):
+    """For triangle pairs (T[b], U[b]), TRI(order) x TRI(order) (TRI(2) by default):
     IA[b, i, j] = int int (r - v_i) . G_r(r, r') . (r' - v_j) and IS[b] = int int phi_r."""
     from . import mgf
-    pts, w = _tri_rule(g)
+    pts, w = _tri_rule(g, order)
     q = pts.shape[1]
     ro = np.repeat(pts[T], q, axis=1).reshape(-1, 3)
     rs = np.tile(pts[U], (1, q, 1)).reshape(-1, 3)
@@ -348,14 +348,14 @@ def _reflected_pair_integrals(g: RWG, freq, stack, T, U):
     return IA, IS
 
 
-def reflected_entries(g: RWG, freq, stack, m, n):
+def reflected_entries(g: RWG, freq, stack, m, n, order=REFL_ORDER):
     """Reflected part of L_A[m, n] (RWG pairs) from the triangle-pair integrals above."""
     m = np.asarray(m)
     n = np.asarray(n)
     Tm = np.stack([g.tplus[m], g.tminus[m]], 1)
     Tn = np.stack([g.tplus[n], g.tminus[n]], 1)
     keys = np.unique(np.concatenate([np.stack([Tm[:, a], Tn[:, b]], 1) for a in range(2) for b in range(2)]), axis=0)
-    IA, _ = _reflected_pair_integrals(g, freq, stack, keys[:, 0], keys[:, 1])
+    IA, _ = _reflected_pair_integrals(g, freq, stack, keys[:, 0], keys[:, 1], order)
     key = keys[:, 0] * np.int64(g.n_t) + keys[:, 1]
     out = np.zeros(m.size, dtype=complex)
     for a in range(2):
@@ -369,11 +369,11 @@ def reflected_entries(g: RWG, freq, stack, m, n):
     return out
 
 
-def reflected_phi_entries(g: RWG, freq, stack, t, u):
-    """Reflected part of L_phi[t, u] = 1/(A_t A_u) int int phi_r, TRI(2) x TRI(2)."""
+def reflected_phi_entries(g: RWG, freq, stack, t, u, order=REFL_ORDER):
+    """Reflected part of L_phi[t, u] = 1/(A_t A_u) int int phi_r, TRI(order) x TRI(order)."""
     t = np.asarray(t)
     u = np.asarray(u)
-    _, IS = _reflected_pair_integrals(g, freq, stack, t, u)
+    _, IS = _reflected_pair_integrals(g, freq, stack, t, u, order)
     return IS / (g.area[t] * g.area[u])
 
 

@@ -120,3 +120,24 @@ def test_layered_aim_matches_dense_layered_operator(two_boxes, reflected_dense):
     # the reflected part matters here: dropping it changes the product by far more
     LA0 = aim.exact_entries(g, k0, m.ravel(), n.ravel()).reshape(g.n_e, g.n_e)
     assert np.linalg.norm(LA0 @ j - LA @ j) > 20 * ea * np.linalg.norm(LA @ j)
+
+
+def test_reflected_rule_converges(two_boxes):
+    """The TRI(2) reading of the reflected near entries against higher-order rules.
+
+    The reflected kernel is smooth at the triangle scale.  On the full two-box operator,
+    TRI(2) is within 2.7e-3 (L_A) and 5e-4 (L_phi) of TRI(5).  Here a few rows are
+    checked (rows 0 and 30, every other column): TRI(2) within 1e-2 of TRI(4), and TRI(3)
+    closer to TRI(4) than TRI(2) is.
+    """
+    g, grid = two_boxes
+    st = mgf.substrate_c4()
+    st.z_if = grid.origin[2] - 1 * UM
+    m, n = np.meshgrid([0, 30], np.arange(0, g.n_e, 2), indexing='ij')
+    A = {o: aim.reflected_entries(g, FREQ, st, m.ravel(), n.ravel(), o) for o in (2, 3, 4)}
+    e2 = np.linalg.norm(A[2] - A[4]) / np.linalg.norm(A[4])
+    e3 = np.linalg.norm(A[3] - A[4]) / np.linalg.norm(A[4])
+    assert e2 < 1e-2 and e3 < 0.5 * e2, (e2, e3)
+    t, u = np.meshgrid([0, 20], np.arange(0, g.n_t, 2), indexing='ij')
+    P = {o: aim.reflected_phi_entries(g, FREQ, st, t.ravel(), u.ravel(), o) for o in (2, 4)}
+    assert np.linalg.norm(P[2] - P[4]) / np.linalg.norm(P[4]) < 2e-3
