@@ -191,8 +191,18 @@ def _integrals(ra, wa, rb, wb, Pa, Pb, k, want_k):
     return IA, S0, IK
 
 
-def pair_integrals(Va, Vb, k, near, coplanar, qp: QuadParams, want_k=True, batch=64, direct=False):
-    """IA (B,3,3), IS (B,), IK (B,3,3) for triangle pairs (Va[b], Vb[b])."""
+DEFAULT_DIRECT = True
+
+
+def pair_integrals(Va, Vb, k, near, coplanar, qp: QuadParams, want_k=True, batch=64, direct=None):
+    """IA (B,3,3), IS (B,), IK (B,3,3) for triangle pairs (Va[b], Vb[b]).
+
+    The sums are taken term by term (_integrals_direct) unless direct=False asks for
+    the centroid-moment form (_integrals), a faster rearrangement of the same sums
+    that the tests pin against the direct one on both rules.
+    """
+    if direct is None:
+        direct = DEFAULT_DIRECT
     B = Va.shape[0]
     IA = np.zeros((B, 3, 3), dtype=complex)
     IS = np.zeros(B, dtype=complex)

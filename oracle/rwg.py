@@ -169,3 +169,31 @@ def project_tangential(g: RWG, field_fn, order=6):
         for i in range(3):
             b[g.tri_edge[t, i]] += np.sum(w[:, None] * rwg_on_triangle(g, t, i, pts) * F)
     return np.linalg.solve(Gm, b), Gm
+
+
+def interpolate_tangential(g: RWG, field_fn, n=8):
+    """RWG interpolant of a tangential field F by edge fluxes (Rao-Wilton-Glisson).
+
+    f_n carries unit normal flux density across its own edge and none across the
+    others, so the coefficient of edge n is the mean, along the edge, of F . m_n,
+    with m_n the unit vector in the plane of T+ normal to the edge and pointing
+    away from the free vertex of T+.  F is evaluated on the T+ side
+    (field_fn(points, triangle)).  Unlike the Gram projection, this interpolant
+    keeps the flux of F across every edge, hence the triangle-averaged surface
+    divergence.
+    """
+    from .quad import gauss01
+    x, w = gauss01(n)
+    c = np.zeros(g.n_e, dtype=complex)
+    for e in range(g.n_e):
+        t = int(g.tplus[e])
+        i = int(np.nonzero(g.tri_edge[t] == e)[0][0])
+        p = g.verts[g.tris[t, i]]
+        a, b = g.verts[g.edge_v[e, 0]], g.verts[g.edge_v[e, 1]]
+        tt = (b - a) / np.linalg.norm(b - a)
+        m = 0.5 * (a + b) - p
+        m = m - np.dot(m, tt) * tt
+        m = m / np.linalg.norm(m)
+        pts = a[None, :] + x[:, None] * (b - a)[None, :]
+        c[e] = np.sum(w * (np.asarray(field_fn(pts, t)) @ m))
+    return c

@@ -100,3 +100,65 @@ def test_near_rule_converges():
             for u, v, tol in zip(x1, x2, (3e-3, 3e-3, 5e-3)):
                 if np.abs(v).max() > 0:
                     assert np.abs(u - v).max() <= tol * np.abs(v).max()
+
+
+def test_far_rule_self_convergence_and_moment_form():
+    """TRI(n) x TRI(n) on separated pairs converges to 1e-10 as n grows (P-Q1); the default
+    TRI(4) stays within 2e-4 of the converged value; the moment form equals the direct sum."""
+    a = np.array([[0, 0, 0], [1.0, 0, 0], [0, 1.0, 0]]) * 1e-6
+    for shift in (2.5, 4.0, 8.0):
+        b = a + np.array([shift, 0.5, 0.3]) * 1e-6
+        for k in (1e5 + 0j, 1.5e6 - 1.5e6j):
+            cop = np.array([False])
+            x = {n: pair_integrals(a[None], b[None], k, False, cop, QuadParams(n_far=n)) for n in (4, 12, 16)}
+            for u, v, w in zip(x[12], x[16], x[4]):
+                assert np.abs(u - v).max() <= 1e-10 * np.abs(v).max()
+                assert np.abs(w - v).max() <= 2e-4 * np.abs(v).max()
+            xm = pair_integrals(a[None], b[None], k, False, cop, QuadParams(), direct=False)
+            for u, v in zip(xm, x[4]):
+                assert np.abs(u - v).max() <= 1e-12 * np.abs(v).max()
+
+
+def _subtraction_reference(Va, Vb, k, n=32):
+    """int_Ta int_Tb G by singularity subtraction, independent of the polar rule:
+    the 1/R part in closed form (potential_1_over_R), the smooth remainder
+    (e^{-jkR} - 1)/R with TRI(n) x TRI(n)."""
+    ra, wa = tri_points(Va[None], n)
+    rb, wb = tri_points(Vb[None], n)
+    tot = 0.0
+    for r, w in zip(ra[0], wa[0]):
+        R = np.linalg.norm(rb[0] - r, axis=1)
+        Rs = np.where(R > 0, R, 1.0)
+        smooth = np.where(R > 0, (np.exp(-1j * k * Rs) - 1.0) / Rs, -1j * k)     # its limit at R = 0
+        tot += w * (np.sum(wb[0] * smooth) + potential_1_over_R(r, Vb))
+    return tot / (4.0 * np.pi)
+
+
+HIGH_SIGMA_RULE = QuadParams(n_near=8, levels=6, n_r=8, n_t=10)
+
+
+@pytest.mark.parametrize("kh,base_tol,fine_tol", [(0.3, 2e-3, 3e-4), (6.4, 5e-3, 5e-4), (20.3, None, 5e-3)])
+def test_near_rule_against_subtraction_reference(kh, base_tol, fine_tol):
+    """IS of self, edge-adjacent, folded and near-parallel pairs of 3 um triangles (P-Q2).
+    |k| h = 0.3 is a free-space-like kernel; 6.4 and 20.3 are copper at 10 GHz and 100 GHz
+    (k_c = (1 - j)/delta).  The default near rule holds its stated accuracy up to
+    |k| h ~ 6; at |k| h ~ 20 it does not (up to 45 % on a folded edge pair: the outer
+    TRI(5) does not resolve the e^{-R/delta} layer along the shared edge), and the finer
+    rule HIGH_SIGMA_RULE is the one to build with there."""
+    s = 3e-6
+    a = np.array([[0, 0, 0], [1.0, 0, 0], [0, 1.0, 0]]) * s
+    pairs = {"self": (a, a), "edge": (a, np.array([[1.0, 0, 0], [1.0, 1.0, 0], [0, 1.0, 0]]) * s),
+             "fold": (a, np.array([[1.0, 0, 0], [1.0, 0, 1.0], [1.0, 1.0, 0]]) * s),
+             "par": (a, a + np.array([0.3, 0.2, 0.4]) * s)}
+    k = 1e5 + 0j if kh < 1 else (1 - 1j) * kh / (np.sqrt(2) * s)
+    assert abs(abs(k) * s - kh) < 0.05
+    cop = np.array([False])
+    for name, (Va, Vb) in pairs.items():
+        if kh > 10 and name == "self":
+            continue        # the TRI(32) remainder is not converged itself there
+        ref = _subtraction_reference(Va, Vb, k)
+        fine = pair_integrals(Va[None], Vb[None], k, True, cop, HIGH_SIGMA_RULE)[1][0]
+        assert abs(fine - ref) <= fine_tol * abs(ref), (name, abs(fine - ref) / abs(ref))
+        if base_tol is not None:
+            base = pair_integrals(Va[None], Vb[None], k, True, cop, QuadParams())[1][0]
+            assert abs(base - ref) <= base_tol * abs(ref), (name, abs(base - ref) / abs(ref))
