@@ -110,12 +110,25 @@ typedef struct {
   int64_t precond_budget; /* bytes for the stored blocks and their build buffers;
                              0 = the free device memory after the rest of the build,
                              less room for the solver's Krylov vectors               */
+  /* Kernel shapes.  With slots = 0 the build times the whole mixed product for every
+     combination of the values marked "auto" and keeps the fastest (autotuning). */
+  int32_t fft_zblock;     /* z planes interleaved row by row per block in the FFT
+                             work array between the y and z passes: 1 (plain
+                             [z][y][x]) or 8 ([z/8][y][z%8][x]); 0 = auto          */
+  int32_t rows_per_wave;  /* rows of [Z_i; M_i] one wave of the mixed internal kernel
+                             sweeps together: 4 or 8; 0 = auto                     */
+  const char* tune_cache; /* path of a text file of autotuning results keyed by
+                             (kernel, shape, gfx950), read before and appended after
+                             tuning; NULL = no cache                               */
 } slim_build_opts;
 
 /* Fill `o` with the defaults used by the tests (near_cheb 3, n_far 4, n_near 5,
- * levels 3, q 0.25, n_r 5, n_t 6, c_near 2, LPT, autotuned slot count, graphs on).
- * Autotuning (slots = 0) times the persistent internal kernel for 2, 4 and 8
- * workgroups per compute unit at build time and keeps the fastest.           */
+ * levels 3, q 0.25, n_r 5, n_t 6, c_near 2, LPT, autotuned slot count, plane
+ * z block and rows per wave, graphs on, no tuning cache).
+ * Autotuning (slots = 0) times the whole mixed product for 2, 4 and 8 persistent
+ * internal workgroups per compute unit, times the "auto" kernel shapes, at build
+ * time and keeps the fastest.  A tuning cache entry for the same shape skips the
+ * timing.  With slots > 0 nothing is timed: auto shapes take 64 and 8.         */
 void slim_default_build_opts(slim_build_opts* o);
 
 typedef struct {
@@ -134,6 +147,8 @@ typedef struct {
   int64_t precond_blocks;              /* preconditioner blocks (0: none built)   */
   int64_t precond_entries;             /* stored complex64 entries (rows x ext)   */
   int64_t precond_cap;                 /* cap in effect (0: every conductor whole) */
+  int32_t fft_zblock;                  /* kernel shapes in effect (tuned or given) */
+  int32_t rows_per_wave;
 } slim_layout;
 
 typedef struct {
@@ -187,6 +202,19 @@ slim_status slim_matvec(slim_ctx* ctx, slim_prec prec, const void* x_dev, void* 
  * may be NULL): e = Z H, g = M H, a = L_A j (n_e each), phi = L_phi B c0rho (n_t). */
 slim_status slim_matvec_parts(slim_ctx* ctx, slim_prec prec, const void* x_dev, void* y_dev,
                               void* e_dev, void* g_dev, void* a_dev, void* phi_dev, void* stream);
+/* Y = A X for a block of n_rhs right-hand sides (eq. (7)-(8) applied to every
+ * column).  X, Y: column-major n_sys x n_rhs complex128 device arrays (leading
+ * dimension n_sys), no aliasing, n_rhs >= 1.
+ *   SLIM_MIXED: the internal blocks of up to 64 columns at a time on the matrix
+ *   cores (v_mfma_f32_16x16x32_bf16): every complex64 entry of [Z_i; M_i] and of
+ *   H is split into two BF16 terms, v = v_hi + v_lo, and a b is taken as
+ *   a_hi b_hi + a_hi b_lo + a_lo b_hi with FP32 accumulation (about 2^-16 of |a b|
+ *   per product); the external part then runs column by column.
+ *   SLIM_FP64: every column through the single-column FP64 path.
+ * Enqueues on `stream`; the first call (and a call with more columns than before)
+ * grows a workspace of about (24 n_e + 8 (n_e + 40 n_obj)) bytes per column. */
+slim_status slim_matvec_block(slim_ctx* ctx, slim_prec prec, const void* X_dev, void* Y_dev, int32_t n_rhs,
+                              void* stream);
 /* Internal part only (eq. (4)-(6) applied blockwise): e = Z H, g = M H.  The
  * internal kernel's makespan (persistent launch) is returned in *ms if non-NULL
  * (synchronous when ms != NULL). */
@@ -246,7 +274,10 @@ typedef struct slim_medium {
  *   steps per axis).
  * Replaces any earlier medium.  A STATE or ARG error leaves the context
  * unchanged.  A later failure (UNSUPPORTED, OOM, HIP) leaves it without a
- * medium, with its free-space near field.
+ * medium, with its free-space near field; if even those values cannot be
+ * restored, the context is left unbuilt (products then return SLIM_E_STATE).
+ * slim_build always starts again in free space: a medium does not survive a
+ * rebuild and must be set again.
  *
  * slim_aim_convolve_layered: the four grid components (x, y, z current and
  *   charge; 4 x Nx Ny Nz complex128 device arrays, node order x fastest),
@@ -274,6 +305,35 @@ slim_status slim_layered_gammas(const slim_medium* medium, double freq, int64_t 
 slim_status slim_aim_convolve_layered(slim_ctx* ctx, slim_prec prec, const void* src_dev, void* dst_dev, void* stream);
 slim_status slim_get_layered_kernels(const slim_ctx* ctx, double* out);
 slim_status slim_get_near(const slim_ctx* ctx, int32_t which, int64_t* ptr, int32_t* col, double* val);
+
+/* Lumped ports (Sec. II: excitation "by lumped ports").  A port is an ideal
+ * voltage source across a cut of one conductor's surface: the closed ring of mesh
+ * edges of object `obj` that lie in the plane through `point` normal to `axis`
+ * and within `radius` of `point`.  Its incident field is V delta(s) axis (s the
+ * distance from the plane along axis), so testing with f_m gives
+ *   b1[m] = (V / eta0) s_m l_m on the ring edges, 0 elsewhere; b2 = 0,
+ * with s_m = +1 or -1 as the edge's RWG function crosses it along or against axis.
+ * The port current along axis is the flux of n x H across the ring,
+ *   I = sum over the ring of s_m l_m H_m,
+ * so with V = 1 the port admittance matrix is Y[p][q] = I_p of the solution for
+ * port q.  SLIM_E_ARG if a ring is empty, not one closed loop, or lies in a face
+ * (an edge whose RWG function crosses it at more than 60 degrees from axis). */
+typedef struct slim_port {
+  int32_t obj;
+  double point[3];
+  double axis[3];
+  double radius;
+} slim_port;
+
+/* B = [b of port 0, ..., b of port n_ports-1] with V = 1 V: column-major
+ * n_sys x n_ports complex128 device array.  Synchronous. */
+slim_status slim_rhs_ports(slim_ctx* ctx, const slim_port* ports, int32_t n_ports, void* B_dev, void* stream);
+/* Port currents of n_rhs solution columns X (column-major n_sys x n_rhs complex128,
+ * device): I_host (host, n_ports x n_rhs complex128 as interleaved doubles,
+ * column-major: I_host[2 (p + n_ports q)] is the real part of I_p of column q).
+ * Synchronous. */
+slim_status slim_port_currents(slim_ctx* ctx, const slim_port* ports, int32_t n_ports, const void* X_dev,
+                               int32_t n_rhs, double* I_host, void* stream);
 
 /* Right-hand side of (7) for an incident plane wave E0 epol e^{-j k0 khat.r}. */
 slim_status slim_rhs_planewave(slim_ctx* ctx, const double khat[3], const double epol[3],
@@ -309,13 +369,20 @@ slim_status slim_precond_partition(const double* xyz, int64_t n_vert, const int3
                                    int64_t* n_blocks, int64_t* n_ext, int64_t* n_own, int64_t* ext_ptr,
                                    int32_t* ext_idx, int64_t* own_ptr, int32_t* own_pos);
 
-/* Per-stage timing of slim_matvec with HIP events recorded on the caller's
- * stream around each kernel group: 0 internal blocks (A1, A2), 1 projection
- * P, 2 FFT convolution (all passes), 3 pulse rows (W, L_phi,NR), 4 RWG rows
- * (W, L_A,NR, combine), 5 continuity rows and casts.  slim_profile(ctx, 1)
- * clears and starts recording; slim_profile_read synchronizes on the last
- * recorded event and returns the summed milliseconds per stage (ms[6]) and
- * the number of matvecs recorded. */
+/* Timing of slim_matvec with HIP events.
+ * slim_profile(ctx, 1): staged products (eager, sequential, the pulse path not
+ *   overlapped) with events recorded on the caller's stream around each kernel
+ *   group: 0 internal blocks (A1, A2), 1 projection P, 2 FFT convolution (all
+ *   passes), 3 pulse rows (W, L_phi,NR), 4 RWG rows (W, L_A,NR, combine),
+ *   5 continuity rows and casts.
+ * slim_profile(ctx, 2): the default path (captured graph, pulse path concurrent),
+ *   with events around each replay on the caller's stream and the internal
+ *   kernel's own wall-clock stamps (first tile start to last tile end) inside it;
+ *   every product then waits for its own end.  ms[0] = internal kernel inside the
+ *   replays, ms[1] = whole replays.
+ * slim_profile(ctx, 0) stops.  Each call clears the sums; slim_profile_read
+ * synchronizes on the last recorded event and returns the summed milliseconds
+ * (ms[6]) and the number of products recorded. */
 slim_status slim_profile(slim_ctx* ctx, int32_t on);
 slim_status slim_profile_read(slim_ctx* ctx, double* ms, int64_t* n_matvec);
 

@@ -172,6 +172,8 @@ Ctx::~Ctx() {
     for (hipEvent_t e : v) (void)hipEventDestroy(e);
   if (ev_fork) (void)hipEventDestroy(ev_fork);
   if (ev_join) (void)hipEventDestroy(ev_join);
+  for (hipEvent_t e : gev)
+    if (e) (void)hipEventDestroy(e);
   if (s_aux) (void)hipStreamDestroy(s_aux);
   if (s_phi) (void)hipStreamDestroy(s_phi);
 }
@@ -301,6 +303,108 @@ static void build_plain_external(Ctx& c, hipStream_t s) {
   SLIM_HIP(hipStreamSynchronize(s));
 }
 
+// ---- autotuning of the kernel shapes --------------------------------------------
+// The whole mixed product is timed (captured graph, pulse path concurrent) for every
+// combination of persistent internal workgroups per compute unit {2, 4, 8}, the
+// auto-valued shapes (z-plane padding of the FFT work array {0, 64}, rows per wave
+// of the internal kernel {4, 8}), two interleaved rounds, best of each.  Results are
+// kept in an optional text cache keyed by (kernel, shape, architecture).
+namespace {
+
+std::string tune_key(const Ctx& c, const char* arch, int cus) {
+  char buf[512];
+  std::snprintf(buf, sizeof(buf), "product|%s|cus=%d|n_e=%lld|n_t=%lld|n_obj=%d|grid=%dx%dx%d|entries=%lld|nnz=%lld+%lld",
+                arch, cus, (long long)c.rwg.n_e, (long long)c.rwg.n_t, c.rwg.n_obj, c.plain ? 0 : c.grid.N[0],
+                c.plain ? 0 : c.grid.N[1], c.plain ? 0 : c.grid.N[2], (long long)c.arena_elems, (long long)c.nnz_A,
+                (long long)c.nnz_P);
+  return buf;
+}
+
+bool tune_cache_lookup(const char* path, const std::string& key, int& per_cu, int& zb, int& rw) {
+  if (!path) return false;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return false;
+  char line[1024];
+  bool found = false;
+  while (std::fgets(line, sizeof(line), f)) {
+    std::string l(line);
+    const size_t bar = l.rfind("|per_cu=");
+    if (bar == std::string::npos || l.compare(0, bar, key) != 0 || bar != key.size()) continue;
+    int a = 0, b = 0, r = 0;
+    if (std::sscanf(l.c_str() + bar, "|per_cu=%d|zblock=%d|rw=%d", &a, &b, &r) == 3 && a > 0 && (b == 1 || b == 8) &&
+        (r == 4 || r == 8)) {
+      per_cu = a; zb = b; rw = r;
+      found = true;   // the last matching line wins
+    }
+  }
+  std::fclose(f);
+  return found;
+}
+
+void tune_cache_store(const char* path, const std::string& key, int per_cu, int zb, int rw, double ms) {
+  if (!path) return;
+  FILE* f = std::fopen(path, "a");
+  if (!f) return;   // an unwritable cache only costs the timing next time
+  std::fprintf(f, "%s|per_cu=%d|zblock=%d|rw=%d|ms=%.4f\n", key.c_str(), per_cu, zb, rw, ms);
+  std::fclose(f);
+}
+
+}  // namespace
+
+static void autotune(Ctx& c, const slim_build_opts& o, hipStream_t s) {
+  int cus = 256;
+  char arch[64] = "unknown";
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, c.device) == hipSuccess) {
+    if (prop.multiProcessorCount > 0) cus = prop.multiProcessorCount;
+    std::snprintf(arch, sizeof(arch), "%s", prop.gcnArchName);
+    if (char* colon = std::strchr(arch, ':')) *colon = '\0';
+  }
+  const int pack_mode = o.sched_mode == 1 ? 0 : o.sched_mode;
+  const std::string key = tune_key(c, arch, cus);
+  int per_cu = 0, zb = 0, rw = 0;
+  if (tune_cache_lookup(o.tune_cache, key, per_cu, zb, rw)) {
+    c.slots = per_cu * cus;
+    c.fft_zsh = zb == 8 ? 3 : 0;
+    c.rw_mixed = rw;
+    pack_tiles(c, pack_mode);
+    if (o.verbose) std::fprintf(stderr, "[slim build] autotune: cached %d per CU, z block %d, rw %d\n", per_cu, zb, rw);
+    return;
+  }
+  SLIM_HIP(hipMemsetAsync(c.d_x64.p, 0, c.d_x64.bytes, s));
+  SLIM_HIP(hipStreamSynchronize(s));
+  std::vector<int> zbs = o.fft_zblock > 0 || c.plain ? std::vector<int>{1 << c.fft_zsh} : std::vector<int>{1, 8};
+  std::vector<int> rws = o.rows_per_wave > 0 ? std::vector<int>{c.rw_mixed} : std::vector<int>{4, 8};
+  const int per_cu_set[3] = {2, 4, 8};
+  struct Cand { int per_cu, zb, rw; double ms; };
+  std::vector<Cand> cand;
+  for (int pc : per_cu_set)
+    for (int z : zbs)
+      for (int r : rws) cand.push_back({pc, z, r, 1e300});
+  for (int round = 0; round < 2; ++round)
+    for (Cand& k : cand) {
+      if (k.per_cu * cus != c.slots) {
+        c.slots = k.per_cu * cus;
+        pack_tiles(c, pack_mode);
+      }
+      c.fft_zsh = k.zb == 8 ? 3 : 0;
+      c.rw_mixed = k.rw;
+      k.ms = std::min(k.ms, time_product(c, 4));
+    }
+  const Cand* best = &cand[0];
+  for (const Cand& k : cand) {
+    if (o.verbose)
+      std::fprintf(stderr, "[slim build] autotune: %d per CU, z block %d, rw %d -> %.3f ms per product\n", k.per_cu,
+                   k.zb, k.rw, k.ms);
+    if (k.ms < best->ms) best = &k;
+  }
+  c.slots = best->per_cu * cus;
+  c.fft_zsh = best->zb == 8 ? 3 : 0;
+  c.rw_mixed = best->rw;
+  pack_tiles(c, pack_mode);
+  tune_cache_store(o.tune_cache, key, best->per_cu, best->zb, best->rw, best->ms);
+}
+
 void build_all(Ctx& c, const slim_build_opts& o) {
   auto t_start = std::chrono::steady_clock::now();
   SLIM_REQUIRE(c.has_mesh, SLIM_E_STATE, "slim_set_mesh must be called before slim_build");
@@ -314,6 +418,27 @@ void build_all(Ctx& c, const slim_build_opts& o) {
                "bytes at one right-hand side");
   SLIM_HIP(hipSetDevice(c.device));
   c.built = false;
+  // A new build starts in free space: the reflected kernels, their spectra and the
+  // kept free-space near values belong to the previous frequency, grid and mesh.
+  c.drop_graphs();
+  c.layered = false;
+  c.lay_zif = 0.0;
+  c.lay_nodes = 0;
+  c.d_lay_real.release();
+  c.d_rhat128.release();
+  c.d_rhat64.release();
+  c.d_lay.release();
+  c.d_nA_free.release();
+  c.d_nP_free.release();
+  // the block product's workspace is laid out for the old mesh
+  c.blk_ldh = 0;
+  c.blk_cols = 0;
+  c.d_blk_hs.release();
+  c.d_blk_h64.release();
+  c.d_blk_e.release();
+  c.d_blk_j.release();
+  c.d_blk_hoff.release();
+  c.d_blk_hpos.release();
   c.opts = o;
   c.freq = o.freq;
   c.omega = 2.0 * kPi * o.freq;
@@ -379,34 +504,16 @@ void build_all(Ctx& c, const slim_build_opts& o) {
   c.tile_rows = o.tile_rows > 0 ? o.tile_rows : 64;
   c.sched_mode = o.sched_mode;
   c.drop_graphs();
+  SLIM_REQUIRE(o.fft_zblock == 0 || o.fft_zblock == 1 || o.fft_zblock == 8, SLIM_E_ARG, "fft_zblock must be 0, 1 or 8");
+  SLIM_REQUIRE(o.rows_per_wave == 0 || o.rows_per_wave == 4 || o.rows_per_wave == 8, SLIM_E_ARG,
+               "rows_per_wave must be 0, 4 or 8");
+  c.fft_zsh = o.fft_zblock == 1 ? 0 : 3;
+  c.rw_mixed = o.rows_per_wave > 0 ? o.rows_per_wave : 8;
   if (o.slots > 0) {
     c.slots = o.slots;
     pack_tiles(c, o.sched_mode);
   } else {
-    // autotune the number of persistent workgroups of the internal kernel on the
-    // whole mixed product: fewer workgroups leave room for the concurrent pulse path
-    int cus = 256;
-    hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, c.device) == hipSuccess && prop.multiProcessorCount > 0) cus = prop.multiProcessorCount;
-    SLIM_HIP(hipMemsetAsync(c.d_x64.p, 0, c.d_x64.bytes, s));
-    SLIM_HIP(hipStreamSynchronize(s));
-    int best = 0;
-    double best_ms = 1e300;
-    std::vector<double> t_slot(3, 1e300);
-    const int per_cu_set[3] = {2, 4, 8};
-    for (int round = 0; round < 2; ++round)   // two interleaved rounds, best of each: less noise
-      for (int k = 0; k < 3; ++k) {
-        c.slots = per_cu_set[k] * cus;
-        pack_tiles(c, o.sched_mode == 1 ? 0 : o.sched_mode);
-        t_slot[k] = std::min(t_slot[k], time_product(c, 4));
-      }
-    for (int k = 0; k < 3; ++k) {
-      if (o.verbose)
-        std::fprintf(stderr, "[slim build] autotune: %d slots -> %.3f ms per product\n", per_cu_set[k] * cus, t_slot[k]);
-      if (t_slot[k] < best_ms) { best_ms = t_slot[k]; best = per_cu_set[k] * cus; }
-    }
-    c.slots = best;
-    pack_tiles(c, o.sched_mode == 1 ? 0 : o.sched_mode);
+    autotune(c, o, s);
   }
   SLIM_HIP(hipStreamSynchronize(s));
   build_precond(c, s);
@@ -433,6 +540,8 @@ void build_all(Ctx& c, const slim_build_opts& o) {
   Lo.precond_blocks = c.pc_built ? int64_t(c.pc_blocks.size()) : 0;
   Lo.precond_entries = c.pc_built ? c.pc_entries : 0;
   Lo.precond_cap = c.pc_cap;
+  Lo.fft_zblock = c.plain ? 0 : 1 << c.fft_zsh;
+  Lo.rows_per_wave = c.rw_mixed;
   c.built = true;
 }
 

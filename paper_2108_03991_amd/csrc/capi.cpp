@@ -57,6 +57,9 @@ void slim_default_build_opts(slim_build_opts* o) {
   o->precond_overlap = 2;
   o->precond_cap = 0;
   o->precond_budget = 0;
+  o->fft_zblock = 0;
+  o->rows_per_wave = 0;
+  o->tune_cache = nullptr;
 }
 
 slim_status slim_create(int32_t hip_device, slim_ctx** out) {
@@ -173,6 +176,17 @@ slim_status slim_matvec_parts(slim_ctx* h, slim_prec prec, const void* x, void* 
   });
 }
 
+slim_status slim_matvec_block(slim_ctx* h, slim_prec prec, const void* X, void* Y, int32_t n_rhs, void* stream) {
+  return guard(h, [&]() {
+    SLIM_REQUIRE(h->c.built, SLIM_E_STATE, "operator not built");
+    SLIM_REQUIRE(X && Y && X != Y && n_rhs >= 1, SLIM_E_ARG, "X and Y must be distinct device arrays, n_rhs >= 1");
+    SLIM_REQUIRE(prec == SLIM_FP64 || prec == SLIM_MIXED, SLIM_E_ARG, "unknown precision");
+    SLIM_HIP(hipSetDevice(h->c.device));
+    matvec_block(h->c, prec, X, Y, n_rhs, as_stream(stream));
+    return SLIM_OK;
+  });
+}
+
 slim_status slim_internal_apply(slim_ctx* h, slim_prec prec, const void* H, void* e, void* g, double* ms, void* stream) {
   return guard(h, [&]() {
     SLIM_REQUIRE(h->c.built, SLIM_E_STATE, "operator not built");
@@ -238,6 +252,44 @@ slim_status slim_rhs_planewave(slim_ctx* h, const double khat[3], const double e
     }
     SLIM_HIP(hipMemcpyAsync(b, out.data(), out.size() * 16, hipMemcpyHostToDevice, as_stream(stream)));
     SLIM_HIP(hipStreamSynchronize(as_stream(stream)));
+    return SLIM_OK;
+  });
+}
+
+slim_status slim_rhs_ports(slim_ctx* h, const slim_port* ports, int32_t n_ports, void* B, void* stream) {
+  return guard(h, [&]() {
+    SLIM_REQUIRE(h->c.built, SLIM_E_STATE, "operator not built");
+    SLIM_REQUIRE(ports && B && n_ports >= 1, SLIM_E_ARG, "null or empty port list");
+    SLIM_HIP(hipSetDevice(h->c.device));
+    const RWGTable& r = h->c.rwg;
+    const int64_t nsys = r.n_e + r.n_t;
+    std::vector<cd> out(size_t(nsys) * n_ports, cd(0.0));
+    for (int p = 0; p < n_ports; ++p) {
+      std::vector<int32_t> edges;
+      std::vector<double> w;
+      port_ring(h->c, ports[p], edges, w);
+      for (size_t k = 0; k < edges.size(); ++k) out[size_t(p) * nsys + edges[k]] = cd(w[k] / eta0(), 0.0);
+    }
+    hipStream_t s = as_stream(stream);
+    SLIM_HIP(hipMemcpyAsync(B, out.data(), out.size() * 16, hipMemcpyHostToDevice, s));
+    SLIM_HIP(hipStreamSynchronize(s));
+    return SLIM_OK;
+  });
+}
+
+slim_status slim_port_currents(slim_ctx* h, const slim_port* ports, int32_t n_ports, const void* X, int32_t n_rhs,
+                               double* I, void* stream) {
+  return guard(h, [&]() {
+    SLIM_REQUIRE(h->c.built, SLIM_E_STATE, "operator not built");
+    SLIM_REQUIRE(ports && X && I && n_ports >= 1 && n_rhs >= 1, SLIM_E_ARG, "null or empty argument");
+    SLIM_HIP(hipSetDevice(h->c.device));
+    std::vector<int32_t> edges, start(1, 0);
+    std::vector<double> w;
+    for (int p = 0; p < n_ports; ++p) {
+      port_ring(h->c, ports[p], edges, w);
+      start.push_back(int32_t(edges.size()));
+    }
+    port_currents(h->c, edges, w, start, X, n_rhs, I, as_stream(stream));
     return SLIM_OK;
   });
 }
@@ -346,7 +398,7 @@ slim_status slim_set_medium(slim_ctx* h, const slim_medium* m) {
   return guard(h, [&]() {
     SLIM_REQUIRE(m, SLIM_E_ARG, "null medium");
     SLIM_HIP(hipSetDevice(h->c.device));
-    h->c.layered = false;
+    // build_layered validates every argument before it changes any state
     build_layered(h->c, *m, h->c.s_aux);
     return SLIM_OK;
   });
@@ -422,9 +474,18 @@ slim_status slim_get_near(const slim_ctx* hc, int32_t which, int64_t* ptr, int32
 
 slim_status slim_profile(slim_ctx* h, int32_t on) {
   return guard(h, [&]() {
-    h->c.prof_on = on != 0;
+    SLIM_REQUIRE(on >= 0 && on <= 2, SLIM_E_ARG, "profile mode must be 0, 1 or 2");
+    const bool graph = on == 2;
+    if (graph != h->c.gprof_on) h->c.drop_graphs();   // the event nodes are part of the captured product
+    if (graph)
+      for (hipEvent_t& e : h->c.gev)
+        if (!e) SLIM_HIP(hipEventCreate(&e));
+    h->c.prof_on = on == 1;
+    h->c.gprof_on = graph;
     for (auto& u : h->c.prof_used) u = 0;
     h->c.prof_calls = 0;
+    h->c.gprof_ms[0] = h->c.gprof_ms[1] = 0.0;
+    h->c.gprof_calls = 0;
     return SLIM_OK;
   });
 }
@@ -432,6 +493,13 @@ slim_status slim_profile(slim_ctx* h, int32_t on) {
 slim_status slim_profile_read(slim_ctx* h, double* ms, int64_t* n_matvec) {
   return guard(h, [&]() {
     SLIM_REQUIRE(ms, SLIM_E_ARG, "null output");
+    if (h->c.gprof_on) {
+      for (int st = 0; st < 6; ++st) ms[st] = 0.0;
+      ms[0] = h->c.gprof_ms[0];
+      ms[1] = h->c.gprof_ms[1];
+      if (n_matvec) *n_matvec = h->c.gprof_calls;
+      return SLIM_OK;
+    }
     for (int st = 0; st < 6; ++st) {
       double tot = 0.0;
       const size_t used = h->c.prof_used[st];

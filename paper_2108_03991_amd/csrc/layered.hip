@@ -568,7 +568,7 @@ void layered_gammas(const slim_medium& md, double freq, int64_t n, const double*
 }
 
 static void build_layered_device(Ctx& c, const slim_medium& md, const Stack& st, double d_min, double z0, hipStream_t s);
-static void restore_free_near(Ctx& c);
+static bool restore_free_near(Ctx& c, hipStream_t s);
 
 void build_layered(Ctx& c, const slim_medium& md, hipStream_t s) {
   SLIM_REQUIRE(c.built && !c.plain, SLIM_E_STATE, "no AIM operator built");
@@ -599,25 +599,32 @@ void build_layered(Ctx& c, const slim_medium& md, hipStream_t s) {
   try {
     build_layered_device(c, md, st, d_min, z0, s);
   } catch (...) {
-    // a device failure leaves the context without a medium, with its free-space near field
-    restore_free_near(c);
+    // a device failure leaves the context without a medium, with its free-space near
+    // field; if even that cannot be restored, the context is marked unbuilt so that no
+    // product runs on half-corrected values
+    if (!restore_free_near(c, s)) c.built = false;
     throw;
   }
   c.layered = true;
   c.lay_zif = md.z_interface;
 }
 
-static void restore_free_near(Ctx& c) {
+static bool restore_free_near(Ctx& c, hipStream_t s) {
+  // the failed build may still have kernels and copies queued on s that write the
+  // near-field values: wait for them before copying the kept values back
+  bool ok = hipStreamSynchronize(s) == hipSuccess;
   for (int which = 0; which < 2; ++which) {
     DevBuf& fr = which == 0 ? c.d_nA_free : c.d_nP_free;
     DevBuf& v128 = which == 0 ? c.d_nA_v128 : c.d_nP_v128;
     DevBuf& v64 = which == 0 ? c.d_nA_v64 : c.d_nP_v64;
     const int64_t nnz = which == 0 ? c.nnz_A : c.nnz_P;
     if (!fr.p || nnz == 0) continue;
-    if (hipMemcpy(v128.p, fr.p, v128.bytes, hipMemcpyDeviceToDevice) != hipSuccess) continue;
-    hipLaunchKernelGGL(k_c128_to_c64_n, dim3(nblk(nnz)), dim3(256), 0, 0, v128.as<double2>(), v64.as<float2>(), nnz);
-    (void)hipDeviceSynchronize();
+    if (hipMemcpyAsync(v128.p, fr.p, v128.bytes, hipMemcpyDeviceToDevice, s) != hipSuccess) { ok = false; continue; }
+    hipLaunchKernelGGL(k_c128_to_c64_n, dim3(nblk(nnz)), dim3(256), 0, s, v128.as<double2>(), v64.as<float2>(), nnz);
+    if (hipGetLastError() != hipSuccess) ok = false;
   }
+  if (hipStreamSynchronize(s) != hipSuccess) ok = false;
+  return ok;
 }
 
 static void build_layered_device(Ctx& c, const slim_medium& md, const Stack& st, double d_min, double z0,

@@ -102,3 +102,65 @@ def test_layered_graph_and_medium_replacement(layered_case):
     ne = lay.n_e
     assert rel(got[:ne], ref[:ne]) <= 1e-6 and rel(got[ne:], ref[ne:]) <= 1e-6
     assert rel(free[:ne], ref[:ne]) > 1e-3        # the substrate changes the RWG rows
+
+
+def _free_case(m, freq, N):
+    from oracle import aim
+    from oracle.operators import Physics, interior_blocks
+    from oracle.rwg import build_rwg, matrix_D, matrix_Ix_and_gram
+    g = build_rwg(m.verts, m.tris, m.obj, m.n_obj)
+    ph = Physics(freq)
+    grid = aim.make_grid(g.verts, N)
+    op = aim.build_aim(g, grid, ph.k0, lambda a, b: aim.exact_entries(g, ph.k0, a, b),
+                       lambda a, b: aim.exact_phi_entries(g, ph.k0, a, b))
+    Ix, _ = matrix_Ix_and_gram(g)
+    return (m, g, ph, op, Ix, matrix_D(g), interior_blocks(g, ph, Ix=Ix))
+
+
+def test_rebuild_starts_in_free_space(layered_case):
+    """A build after a medium was set is a free-space operator again (here at another
+    frequency and on a larger grid, where the old reflected spectra would not even fit),
+    and a medium set after a further rebuild matches the layered oracle."""
+    case, st = layered_case
+    m = case[0]
+    ctx, lay = context(m, freq=FREQ, grid=(8, 8, 8), precond=0)
+    _set(ctx, st)
+    # 16 x 8 x 8 keeps the grid spacing (0.6 um) of the first build: on a finer grid the
+    # stencils of these 2 um triangles would be too small, the near and grid parts would
+    # cancel to 1/1700 of their size and complex64 would lose 3e-4 (measured on the CPU)
+    lay2 = ctx.build(freq=5e9, grid=(16, 8, 8), precond=0)
+    free = _free_case(m, 5e9, (16, 8, 8))
+    x = random_complex(lay2.n_sys, 14)
+    for prec in (FP64, MIXED):
+        _check(run_parts(ctx, lay2, prec, x), _parts(free, x), lay2.n_e, prec)
+    lay3 = ctx.build(freq=FREQ, grid=(8, 8, 8), precond=0)
+    _set(ctx, st)
+    _check(run_parts(ctx, lay3, FP64, x), _parts(case, x), lay3.n_e, FP64)
+
+
+def test_bad_medium_leaves_context_unchanged(layered_case):
+    """An argument error of slim_set_medium keeps the medium that was set: the captured and
+    the staged products are bit for bit those from before the failed call."""
+    import torch
+    from paper_2108_03991_amd import slim
+    case, st = layered_case
+    ctx, lay = context(case[0], freq=FREQ, grid=(8, 8, 8), precond=0)
+    _set(ctx, st)
+    x = random_complex(lay.n_sys, 15)
+    xt = torch.tensor(x, device='cuda')
+    y = torch.zeros_like(xt)
+    ctx.matvec(FP64, xt, y)
+    torch.cuda.synchronize()
+    graph0, staged0 = y.cpu().numpy(), run_parts(ctx, lay, FP64, x)['y']
+    for bad in (dict(z_interface=st.z_if, layers=[(-1.0, 11.9, 10.0)], bottom="pec"),
+                dict(z_interface=st.z_if + 1.0, layers=st.layers, bottom="pec")):
+        with pytest.raises(slim.SlimError) as ei:
+            ctx.set_medium(**bad)
+        assert ei.value.code == 1
+        y.zero_()
+        ctx.matvec(FP64, xt, y)
+        torch.cuda.synchronize()
+        assert np.array_equal(y.cpu().numpy(), graph0)
+        assert np.array_equal(run_parts(ctx, lay, FP64, x)['y'], staged0)
+    ref = _parts(case, x)['y']
+    assert rel(graph0[:lay.n_e], ref[:lay.n_e]) <= 1e-6
