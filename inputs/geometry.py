@@ -136,6 +136,33 @@ def split_ring_mesh(center, r_mid, width, thick, gap, n_theta):
     return verts, tris
 
 
+def ring_mesh(center, r_mid, width, thick, n_theta):
+    """Closed ring of rectangular section (a split ring without its gap): a genus-1
+    surface of 8*n_theta triangles.  Station s sits at angle 2 pi s / n_theta; its four
+    section corners are (r_in, z0), (r_out, z0), (r_out, z1), (r_in, z1)."""
+    cx, cy, cz = (float(c) for c in center)
+    rin, rout = r_mid - width / 2.0, r_mid + width / 2.0
+    verts = []
+    for s in range(n_theta):
+        th = 2.0 * math.pi * s / n_theta
+        ct, st = math.cos(th), math.sin(th)
+        for r, z in ((rin, 0.0), (rout, 0.0), (rout, thick), (rin, thick)):
+            verts.append((cx + r * ct, cy + r * st, cz + z))
+    verts = np.asarray(verts, dtype=np.float64)
+    tl, nl = [], []
+    for s in range(n_theta):
+        s1 = (s + 1) % n_theta
+        thm = 2.0 * math.pi * (s + 0.5) / n_theta
+        rh = np.array([math.cos(thm), math.sin(thm), 0.0])
+        for (c0, c1), n in (((0, 1), (0.0, 0.0, -1.0)), ((1, 2), tuple(rh)), ((2, 3), (0.0, 0.0, 1.0)),
+                            ((3, 0), tuple(-rh))):
+            a, b, c, d = 4 * s + c0, 4 * s + c1, 4 * s1 + c1, 4 * s1 + c0
+            tl += [(a, b, c), (a, c, d)]
+            nl += [n, n]
+    tris = np.asarray(_orient(tl, verts, np.asarray(nl)), dtype=np.int32)
+    return verts, tris
+
+
 def merge(parts):
     """Concatenate (verts, tris) parts into one Mesh; part k becomes object k."""
     vs, ts, os_ = [], [], []

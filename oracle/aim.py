@@ -274,11 +274,13 @@ def exact_phi_entries(g: RWG, k0, t, u, qp=None):
     return IS / (g.area[t] * g.area[u])
 
 
-def convolve_layered_direct(grid: Grid, freq, stack, src):
+def convolve_layered_direct(grid: Grid, freq, stack, src, targets=None):
     """Grid potentials over a layered medium by brute force over all node pairs (tiny grids only).
 
     src: (4, nodes) grid sources of the x, y, z current components and of the
-    charge.  The kernel is the free-space grid kernel above (G(0) = 0) plus the
+    charge.  targets: node indices (x fastest) at which the potentials are
+    summed; None means every node.  With a few targets the sum stays cheap on
+    larger grids, since every target is still summed over all sources.  The kernel is the free-space grid kernel above (G(0) = 0) plus the
     reflected dyadic of oracle/mgf.py:
       Phi_x = (g + xx_r) * S_x + G_xz * S_z,   Phi_y = (g + xx_r) * S_y + G_yz * S_z,
       Phi_z = G_zx * S_x + G_zy * S_y + (g + zz_r) * S_z,   Phi_rho = (g + phi_r) * S_rho.
@@ -289,13 +291,14 @@ def convolve_layered_direct(grid: Grid, freq, stack, src):
     Nx, Ny, Nz = grid.N
     idx = np.stack(np.meshgrid(np.arange(Nx), np.arange(Ny), np.arange(Nz), indexing='ij'), -1)
     idx = idx.transpose(2, 1, 0, 3).reshape(-1, 3)        # node order x fastest
-    d = idx[:, None, :] - idx[None, :, :]
+    tgt = idx if targets is None else idx[np.asarray(targets)]
+    d = tgt[:, None, :] - idx[None, :, :]
     Gp = grid_kernel_value(grid, k0, d)
     z0 = grid.origin[2] - stack.z_if
     if z0 <= 0:
         raise ValueError("the AIM grid reaches below the interface")
     # reflected kernels on the distinct (|dx|, |dy|, iz + iz') triples
-    ax, ay, s = np.abs(d[..., 0]), np.abs(d[..., 1]), idx[:, None, 2] + idx[None, :, 2]
+    ax, ay, s = np.abs(d[..., 0]), np.abs(d[..., 1]), tgt[:, None, 2] + idx[None, :, 2]
     key = (ax * Ny + ay) * (2 * Nz) + s
     uk, inv = np.unique(key.ravel(), return_inverse=True)
     rho = np.hypot((uk // (2 * Nz)) // Ny * grid.h[0], (uk // (2 * Nz)) % Ny * grid.h[1])
@@ -308,7 +311,7 @@ def convolve_layered_direct(grid: Grid, freq, stack, src):
         cx = np.where(rr > 0, dxm / rr, 0.0)
         cy = np.where(rr > 0, dym / rr, 0.0)
     Sx, Sy, Sz, Sr = src
-    out = np.zeros((4, idx.shape[0]), dtype=complex)
+    out = np.zeros((4, tgt.shape[0]), dtype=complex)
     out[0] = (Gp + xx) @ Sx - (cx * zxr) @ Sz
     out[1] = (Gp + xx) @ Sy - (cy * zxr) @ Sz
     out[2] = (cx * zxr) @ Sx + (cy * zxr) @ Sy + (Gp + zz) @ Sz

@@ -11,7 +11,7 @@ SRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libslim.so")
 BUILD = os.path.join(os.path.dirname(HERE), "_build")
 SOURCES = ["mesh.cpp", "build.cpp", "sched.cpp", "capi.cpp", "quad.hip", "aim.hip", "fft.hip", "kernels.hip",
-           "solve.hip", "mlp.hip", "precond.hip", "layered.hip"]
+           "solve.hip", "mlp.hip", "precond.hip", "layered.hip", "ports.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-fopenmp",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -67,6 +67,7 @@ struct Ctx {
   DevBuf d_tiles, d_slot_start;
   int slots = 0;
   int tile_rows = 64;
+  int rw_mixed = 8;                     // rows per wave of the mixed internal kernel (4 or 8)
   int sched_mode = 0;
   bool record = false;
   DevBuf d_stamps;                      // 2 x n_tiles uint64 timestamps
@@ -95,6 +96,7 @@ struct Ctx {
   // FFT work arrays (4 components)
   DevBuf d_oct_in, d_oct_in32;          // projected sources: complex128 / complex64 (zero off the occupied nodes)
   DevBuf d_oct_out, d_x1, d_x2;         // sized for complex128; complex64 uses the front
+  int fft_zsh = 0;                      // log2 of the z planes interleaved per block in d_x2 (0 or 3)
   // layered background: reflected kernels on the lattice [4][2Nz-1][Ny][Nx] (xx, zz, phi, zx radial),
   // their spectra [5][2Nz][Ny+1][Nx+1] (xx, zz, phi, zx, zy; scaled by 1/(2N)^3) and the
   // full-z work array of the layered z step (4 components, sized for complex128)
@@ -125,6 +127,12 @@ struct Ctx {
   DevBuf d_x64, d_y64;                  // complex64 copies of x / scratch
   DevBuf d_e, d_g, d_j, d_a, d_phi;     // sized for complex128
 
+  // ---- block of right-hand sides (slim_matvec_block, mixed): workspace grown on demand ----
+  DevBuf d_blk_hs, d_blk_h64, d_blk_e, d_blk_j;   // split H planes, complex64 H, e, j (column-major)
+  DevBuf d_blk_hoff, d_blk_hpos;                  // per block: start of its H slice; per edge: position
+  int64_t blk_ldh = 0;                            // length of a column of a split plane
+  int blk_cols = 0;                               // columns the workspace holds
+
   // ---- graphs ----
   struct GraphKey { int prec; const void* x; void* y; };
   std::vector<std::pair<GraphKey, hipGraphExec_t>> graphs;
@@ -139,6 +147,13 @@ struct Ctx {
   size_t prof_used[6] = {0, 0, 0, 0, 0, 0};
   int64_t prof_calls = 0;
   void prof_mark(int stage, hipStream_t s);   // records the next event of the stage
+  // graph-path timing: events around each replay on the caller's stream, and the
+  // internal kernel's own wall-clock stamps inside the replay
+  bool gprof_on = false;
+  hipEvent_t gev[2] = {nullptr, nullptr};
+  int wall_khz = 0;
+  double gprof_ms[2] = {0.0, 0.0};
+  int64_t gprof_calls = 0;
 
   // ---- cost model ----
   std::vector<float> mlp_params;        // trained FP32 parameters (empty: untrained)
@@ -156,6 +171,7 @@ void matvec(Ctx& c, slim_prec prec, const void* x, void* y, void* e_out, void* g
             void* phi_out, hipStream_t s);
 void internal_apply(Ctx& c, slim_prec prec, const void* H, void* e, void* g, hipStream_t s, bool h_is_c128);
 void matvec_graph(Ctx& c, slim_prec prec, const void* x, void* y, hipStream_t s);
+void matvec_block(Ctx& c, slim_prec prec, const void* X, void* Y, int n_rhs, hipStream_t s);
 double time_internal(Ctx& c, int reps);   // ms per launch of the mixed internal kernel
 double time_product(Ctx& c, int reps);    // ms per mixed product
 void launch_cast_c128_to_c64(const void* in, void* out, int64_t n, hipStream_t s);
@@ -175,6 +191,11 @@ void aim_convolve_layered(Ctx& c, bool fp64, hipStream_t s);   // oct_in -> oct_
 // layered.hip
 void build_layered(Ctx& c, const slim_medium& m, hipStream_t s);
 void layered_gammas(const slim_medium& m, double freq, int64_t n, const double* kr, double* out);   // host only
+// ports.cpp: ring edges of a port (appended to edges) and their weights s_m l_m; the
+// currents sum_m w_m X[m + col n_sys] of every port (start: n_ports + 1 offsets) into I
+void port_ring(const Ctx& c, const slim_port& p, std::vector<int32_t>& edges, std::vector<double>& w);
+void port_currents(Ctx& c, const std::vector<int32_t>& edges, const std::vector<double>& w,
+                   const std::vector<int32_t>& start, const void* X, int n_rhs, double* I, hipStream_t s);
 // sched.cpp
 void pack_tiles(Ctx& c, int mode);
 // precond.hip

@@ -120,9 +120,18 @@ __device__ void fft_batch(C2<T>* lds, const C2<T>* tw) {
   if (rem == 2) { stage<T, L, 2, ELEMS, INV>(lds, Ns, tw); }
 }
 
+// Offset of index i along an axis of stride lo; a blocked axis (sh > 0) splits i into
+// (i >> sh, i & (2^sh - 1)) with strides (hi, lo).
+__device__ __forceinline__ int64_t boff(int i, int64_t lo, int64_t hi, int sh) {
+  return sh ? int64_t(i >> sh) * hi + int64_t(i & ((1 << sh) - 1)) * lo : int64_t(i) * lo;
+}
+
 struct PassArgs {
   const void* in; void* out;
   int64_t in_e, in_o1, in_o2, out_e, out_o1, out_o2;
+  // blocked element (e) and outer (o2) axes of the z-block layout: strides of the block index
+  int64_t in_e_hi, in_o2_hi, out_e_hi, out_o2_hi;
+  int in_e_sh, in_o2_sh, out_e_sh, out_o2_sh;
   int n1, n2;            // line counts along the two outer indices
   int n_in, n_out;       // elements read (others zero) / written per line
   const void* tw;        // L twiddles e^{-2 pi i m / L}
@@ -163,8 +172,6 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_pass(PassArgs a) {
   if (TW_LDS)
     for (int e = threadIdx.x; e < L; e += kFftThreads) tw_lds[e] = reinterpret_cast<const C2<T>*>(a.tw)[e];
   const C2<T>* tw = TW_LDS ? tw_lds : reinterpret_cast<const C2<T>*>(a.tw);
-  const C2<T>* in = reinterpret_cast<const C2<T>*>(a.in) + blockIdx.z * a.comp_in;
-  C2<T>* out = reinterpret_cast<C2<T>*>(a.out) + blockIdx.z * a.comp_out;
   const int g1 = blockIdx.x * W;     // first line along o1
   const int o2 = blockIdx.y;
   // Each thread owns PER elements of the batch.  All of its global loads are issued
@@ -176,6 +183,10 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_pass(PassArgs a) {
     const int e = threadIdx.x + p * kFftThreads;
     if (CONTIG) { b = e / L; i = e % L; } else { b = e % W; i = e / W; }
   };
+  const int64_t in_o2 = boff(o2, a.in_o2, a.in_o2_hi, a.in_o2_sh);
+  const int64_t out_o2 = boff(o2, a.out_o2, a.out_o2_hi, a.out_o2_sh);
+  const C2<T>* in = reinterpret_cast<const C2<T>*>(a.in) + blockIdx.z * a.comp_in;
+  C2<T>* out = reinterpret_cast<C2<T>*>(a.out) + blockIdx.z * a.comp_out;
   {
     C2<T> v[PER];
 #pragma unroll
@@ -184,7 +195,7 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_pass(PassArgs a) {
       coords(p, b, i);
       const int o1 = g1 + b;
       v[p] = {T(0), T(0)};
-      if (o1 < a.n1 && i < a.n_in) v[p] = ld_stream(in + (o1 * a.in_o1 + o2 * a.in_o2 + int64_t(i) * a.in_e));
+      if (o1 < a.n1 && i < a.n_in) v[p] = ld_stream(in + (o1 * a.in_o1 + in_o2 + boff(i, a.in_e, a.in_e_hi, a.in_e_sh)));
     }
 #pragma unroll
     for (int p = 0; p < PER; ++p) {
@@ -223,7 +234,8 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_pass(PassArgs a) {
     int b, i;
     coords(p, b, i);
     const int o1 = g1 + b;
-    if (o1 < a.n1 && i < a.n_out) st_stream(out + (o1 * a.out_o1 + o2 * a.out_o2 + int64_t(i) * a.out_e), lds[pidx<L>(b, i)]);
+    if (o1 < a.n1 && i < a.n_out)
+      st_stream(out + (o1 * a.out_o1 + out_o2 + boff(i, a.out_e, a.out_e_hi, a.out_e_sh)), lds[pidx<L>(b, i)]);
   }
 }
 
@@ -362,8 +374,17 @@ static void convolve_impl(Ctx& c, bool fp64, int ncomp, hipStream_t s, int comp0
   const size_t esz = fp64 ? 16 : 8;
   char* oin = reinterpret_cast<char*>(fp64 ? c.d_oct_in.p : c.d_oct_in32.p) + size_t(comp0) * N3 * esz;
   char* oout = reinterpret_cast<char*>(c.d_oct_out.p) + size_t(comp0) * N3 * esz;
+  // z-block layout of the y-transformed array X2: planes are interleaved row by row in
+  // blocks of B = 2^zsh planes, [z / B][y][z % B][x], so that a z line crosses Nz / B
+  // blocks of B Y2 X2 elements instead of Nz planes of Y2 X2 elements (fewer pages per
+  // line); B = 1 is the plain [z][y][x] order
+  const int zsh = c.fft_zsh;
+  const int64_t ZLO = zsh ? int64_t(X2) : int64_t(X2) * Y2, ZHI = int64_t(X2) * Y2 << zsh, YST = int64_t(X2) << zsh;
+  const int64_t CS2 = 4 * N3;
   char* x1 = reinterpret_cast<char*>(c.d_x1.p) + size_t(comp0) * 2 * N3 * esz;
-  char* x2 = reinterpret_cast<char*>(c.d_x2.p) + size_t(comp0) * 4 * N3 * esz;
+  char* x2 = reinterpret_cast<char*>(c.d_x2.p) + size_t(comp0) * CS2 * esz;
+  auto z_axis_in = [&](PassArgs& a) { a.in_e = ZLO; a.in_e_hi = ZHI; a.in_e_sh = zsh; };
+  auto z_axis_out = [&](PassArgs& a) { a.out_e = ZLO; a.out_e_hi = ZHI; a.out_e_sh = zsh; };
   auto run = [&](auto tag) {
     using T = decltype(tag);
     const C2<T>* tw = reinterpret_cast<const C2<T>*>(fp64 ? c.d_tw128.p : c.d_tw64.p);
@@ -380,21 +401,21 @@ static void convolve_impl(Ctx& c, bool fp64, int ncomp, hipStream_t s, int comp0
     a = PassArgs{};
     a.in = x1; a.out = x2;
     a.in_e = X2; a.in_o1 = 1; a.in_o2 = int64_t(X2) * Ny;
-    a.out_e = X2; a.out_o1 = 1; a.out_o2 = int64_t(X2) * Y2;
+    a.out_e = YST; a.out_o1 = 1; a.out_o2 = ZLO; a.out_o2_hi = ZHI; a.out_o2_sh = zsh;
     a.n1 = X2; a.n2 = Nz; a.n_in = Ny; a.n_out = Y2;
-    a.comp_in = 2 * N3; a.comp_out = 4 * N3;
+    a.comp_in = 2 * N3; a.comp_out = CS2;
     a.tw = tw + tw_off(c, 1);
     launch_pass_L<T, false, 0>(Y2, a, ncomp, s);
     if (!layered) {
       // z fused: X2 lines (kx, ky), stride X2 Y2; forward, x G^, inverse, keep z < Nz
       a = PassArgs{};
       a.in = x2; a.out = x2;
-      a.in_e = a.out_e = int64_t(X2) * Y2; a.in_o1 = a.out_o1 = 1; a.in_o2 = a.out_o2 = X2;
+      z_axis_in(a); z_axis_out(a); a.in_o1 = a.out_o1 = 1; a.in_o2 = a.out_o2 = YST;
       a.n1 = X2; a.n2 = Y2; a.n_in = Nz; a.n_out = Nz;
       a.mul = fp64 ? c.d_ghat128.p : c.d_ghat64.p;
       a.mul_e = int64_t(Nx + 1) * (Ny + 1); a.mul_o1 = 1; a.mul_o2 = Nx + 1;
       a.h_e = Nz; a.h_o1 = Nx; a.h_o2 = Ny;
-      a.comp_in = a.comp_out = 4 * N3;
+      a.comp_in = a.comp_out = CS2;
       a.tw = tw + tw_off(c, 2);
       launch_pass_L<T, false, 2>(Z2, a, ncomp, s);
     } else {
@@ -406,9 +427,9 @@ static void convolve_impl(Ctx& c, bool fp64, int ncomp, hipStream_t s, int comp0
       char* lay = lay0 + size_t(comp0) * 8 * N3 * esz;
       a = PassArgs{};
       a.in = x2; a.out = lay;
-      a.in_e = a.out_e = int64_t(X2) * Y2; a.in_o1 = a.out_o1 = 1; a.in_o2 = a.out_o2 = X2;
+      z_axis_in(a); a.out_e = int64_t(X2) * Y2; a.in_o1 = a.out_o1 = 1; a.in_o2 = YST; a.out_o2 = X2;
       a.n1 = X2; a.n2 = Y2; a.n_in = Nz; a.n_out = Z2;
-      a.comp_in = 4 * N3; a.comp_out = 8 * N3;
+      a.comp_in = CS2; a.comp_out = 8 * N3;
       a.tw = tw + tw_off(c, 2);
       launch_pass_L<T, false, 0>(Z2, a, ncomp, s);
       const int64_t pairs = int64_t(X2) * Y2 * (Nz + 1);
@@ -421,19 +442,19 @@ static void convolve_impl(Ctx& c, bool fp64, int ncomp, hipStream_t s, int comp0
       SLIM_HIP(hipGetLastError());
       a = PassArgs{};
       a.in = lay; a.out = x2;
-      a.in_e = a.out_e = int64_t(X2) * Y2; a.in_o1 = a.out_o1 = 1; a.in_o2 = a.out_o2 = X2;
+      a.in_e = int64_t(X2) * Y2; z_axis_out(a); a.in_o1 = a.out_o1 = 1; a.in_o2 = X2; a.out_o2 = YST;
       a.n1 = X2; a.n2 = Y2; a.n_in = Z2; a.n_out = Nz;
-      a.comp_in = 8 * N3; a.comp_out = 4 * N3;
+      a.comp_in = 8 * N3; a.comp_out = CS2;
       a.tw = tw + tw_off(c, 2);
       launch_pass_L<T, false, 1>(Z2, a, ncomp, s);
     }
     // y-inv: X2 [Nz][Y2][X2] -> X1 [Nz][Ny][X2] (keep y < Ny)
     a = PassArgs{};
     a.in = x2; a.out = x1;
-    a.in_e = X2; a.in_o1 = 1; a.in_o2 = int64_t(X2) * Y2;
+    a.in_e = YST; a.in_o1 = 1; a.in_o2 = ZLO; a.in_o2_hi = ZHI; a.in_o2_sh = zsh;
     a.out_e = X2; a.out_o1 = 1; a.out_o2 = int64_t(X2) * Ny;
     a.n1 = X2; a.n2 = Nz; a.n_in = Y2; a.n_out = Ny;
-    a.comp_in = 4 * N3; a.comp_out = 2 * N3;
+    a.comp_in = CS2; a.comp_out = 2 * N3;
     a.tw = tw + tw_off(c, 1);
     launch_pass_L<T, false, 1>(Y2, a, ncomp, s);
     // x-inv: X1 [Nz][Ny][X2] -> octant (keep x < Nx)

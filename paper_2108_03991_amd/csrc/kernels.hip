@@ -145,14 +145,14 @@ __device__ __forceinline__ float4 ntload(const float2* p) {
   return make_float4(v.x, v.y, v.z, v.w);
 }
 
-template <bool F64>
+template <bool F64, int RW>
 __global__ void __launch_bounds__(256) k_internal(const float2* __restrict__ hi, const float2* __restrict__ lo,
                                                   const BlockDev* __restrict__ blocks, const int4* __restrict__ tiles,
                                                   const int32_t* __restrict__ slot_start, const void* __restrict__ Hv,
                                                   void* __restrict__ ev, void* __restrict__ jv, void* __restrict__ gv,
                                                   unsigned long long* __restrict__ stamps) {
   using T = typename P<F64>::T;
-  constexpr int RW = F64 ? 4 : 8;    // rows per wave per sweep (hi + lo doubles the loads in FP64)
+  // RW rows per wave per sweep (4 in FP64, where hi + lo doubles the loads; 4 or 8 in mixed)
   const C2<T>* H = reinterpret_cast<const C2<T>*>(Hv);
   C2<T>* e = reinterpret_cast<C2<T>*>(ev);
   C2<T>* jo = reinterpret_cast<C2<T>*>(jv);
@@ -238,6 +238,143 @@ __global__ void __launch_bounds__(256) k_internal(const float2* __restrict__ hi,
       if (threadIdx.x == 0) {
         stamps[2 * ti] = t_start;
         stamps[2 * ti + 1] = wall_clock64();
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// A1 + A2 for a block of right-hand sides (mixed precision) on the matrix cores.
+// Every tile's rows of [Z_i; M_i] multiply up to 64 columns of H at once with
+// v_mfma_f32_16x16x32_bf16.  Split-BF16: a value v (FP32, the hi part of the arena
+// or the complex64 copy of H) is v_hi = bf16(v), v_lo = bf16(v - v_hi); a product
+// a b is taken as a_hi b_hi + a_hi b_lo + a_lo b_hi with FP32 accumulation (the
+// dropped a_lo b_lo and the split remainders are about 2^-16 of |a b|).  The complex
+// product is four real ones, Re = Ar Hr - Ai Hi, Im = Ar Hi + Ai Hr: 12 MFMAs per 32
+// columns of A per 16 right-hand sides.
+// Operand layout of the 16x16x32 MFMA in a wave: lane l holds row (l & 15) of A and
+// column (l & 15) of B, each at K = 8 (l >> 4) ... + 7; the result gives lane l
+// column (l & 15), rows 4 (l >> 4) ... + 3.
+// ---------------------------------------------------------------------------
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ void split_bf16(const float* v, bf16x8& hi, bf16x8& lo) {
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const __bf16 h = __bf16(v[i]);
+    hi[i] = h;
+    lo[i] = __bf16(v[i] - float(h));
+  }
+}
+
+// H (complex128, the first ne entries of the columns of X, leading dimension nsys)
+// -> the complex64 copy H64 [R][ne] and the four split planes Hs[p][col][ldh]
+// (p: re hi, re lo, im hi, im lo).  In a plane, block i starts at a multiple of
+// eight (hpos maps an edge to its position), so that the MFMA kernel's 16-byte
+// loads are aligned; the gaps between blocks stay zero from the allocation.
+__global__ void k_split_h(const double2* X, int64_t nsys, int64_t ne, int R, int64_t ldh, int64_t plane,
+                          const int32_t* hpos, float2* H64, __bf16* Hs) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= int64_t(R) * ne) return;
+  const int col = int(i / ne);
+  const int64_t k = i % ne;
+  const double2 v = X[int64_t(col) * nsys + k];
+  const float re = float(v.x), im = float(v.y);
+  H64[i] = make_float2(re, im);
+  const int64_t o = int64_t(col) * ldh + hpos[k];
+  const __bf16 rh = __bf16(re), ih = __bf16(im);
+  Hs[o] = rh;
+  Hs[plane + o] = __bf16(re - float(rh));
+  Hs[2 * plane + o] = ih;
+  Hs[3 * plane + o] = __bf16(im - float(ih));
+}
+
+template <int NCG>
+__global__ void __launch_bounds__(256) k_internal_mfma(const float2* __restrict__ hi, const BlockDev* __restrict__ blocks,
+                                                       const int4* __restrict__ tiles,
+                                                       const int32_t* __restrict__ slot_start,
+                                                       const int64_t* __restrict__ hoff, const __bf16* __restrict__ Hs,
+                                                       int64_t plane, int64_t ldh,
+                                                       const float2* __restrict__ H64, int64_t ne, int ncol,
+                                                       float2* __restrict__ E, float2* __restrict__ J) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int lr = lane & 15, lg = lane >> 4;
+  for (int ti = slot_start[blockIdx.x]; ti < slot_start[blockIdx.x + 1]; ++ti) {
+    const int4 tl = tiles[ti];
+    const BlockDev B = blocks[tl.x];
+    const int n = B.n, ld = (n + 1) & ~1, rend = tl.y + tl.z;
+    for (int r0 = tl.y + 16 * wave; r0 < rend; r0 += 64) {
+      f32x4 acc[NCG][4];
+#pragma unroll
+      for (int g = 0; g < NCG; ++g)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[g][q] = f32x4{0.f, 0.f, 0.f, 0.f};
+      const int row = r0 + lr;
+      const float2* arow = hi + B.off + int64_t(row) * ld;
+      // A fragment of the K chunk starting at k0: 8 complex (4 pairs), zero past the row
+      auto load_a = [&](int k0, float4* a) {
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+          const int kk = k0 + 8 * lg + 2 * p;
+          a[p] = (row < rend && kk < ld) ? ntload(arow + kk) : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+      };
+      float4 a_cur[4], a_nxt[4];
+      load_a(0, a_cur);
+      for (int k0 = 0; k0 < n; k0 += 32) {
+        if (k0 + 32 < n) load_a(k0 + 32, a_nxt);
+        float re[8], im[8];
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+          re[2 * p] = a_cur[p].x; im[2 * p] = a_cur[p].y;
+          re[2 * p + 1] = a_cur[p].z; im[2 * p + 1] = a_cur[p].w;
+        }
+        bf16x8 arh, arl, aih, ail;
+        split_bf16(re, arh, arl);
+        split_bf16(im, aih, ail);
+        const int64_t kb = hoff[tl.x] + k0 + 8 * lg;
+#pragma unroll
+        for (int g = 0; g < NCG; ++g) {
+          const int64_t o = int64_t(16 * g + lr) * ldh + kb;
+          const bf16x8 hrh = *reinterpret_cast<const bf16x8*>(Hs + o);
+          const bf16x8 hrl = *reinterpret_cast<const bf16x8*>(Hs + plane + o);
+          const bf16x8 hih = *reinterpret_cast<const bf16x8*>(Hs + 2 * plane + o);
+          const bf16x8 hil = *reinterpret_cast<const bf16x8*>(Hs + 3 * plane + o);
+          acc[g][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(arh, hrh, acc[g][0], 0, 0, 0);
+          acc[g][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(arh, hrl, acc[g][0], 0, 0, 0);
+          acc[g][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(arl, hrh, acc[g][0], 0, 0, 0);
+          acc[g][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aih, hih, acc[g][1], 0, 0, 0);
+          acc[g][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aih, hil, acc[g][1], 0, 0, 0);
+          acc[g][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ail, hih, acc[g][1], 0, 0, 0);
+          acc[g][2] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(arh, hih, acc[g][2], 0, 0, 0);
+          acc[g][2] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(arh, hil, acc[g][2], 0, 0, 0);
+          acc[g][2] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(arl, hih, acc[g][2], 0, 0, 0);
+          acc[g][3] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aih, hrh, acc[g][3], 0, 0, 0);
+          acc[g][3] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aih, hrl, acc[g][3], 0, 0, 0);
+          acc[g][3] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ail, hrh, acc[g][3], 0, 0, 0);
+        }
+#pragma unroll
+        for (int p = 0; p < 4; ++p) a_cur[p] = a_nxt[p];
+      }
+      // epilogue: e rows (row < n) and j = H - g rows (row >= n), column 16 g + lr
+#pragma unroll
+      for (int g = 0; g < NCG; ++g) {
+        const int col = 16 * g + lr;
+        if (col >= ncol) continue;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int rr = r0 + 4 * lg + q;
+          if (rr >= rend) continue;
+          const float yr = acc[g][0][q] - acc[g][1][q], yi = acc[g][2][q] + acc[g][3][q];
+          if (rr < n) {
+            E[int64_t(col) * ne + B.e0 + rr] = make_float2(yr, yi);
+          } else {
+            const int64_t k = int64_t(col) * ne + B.e0 + (rr - n);
+            const float2 h = H64[k];
+            J[k] = make_float2(h.x - yr, h.y - yi);
+          }
+        }
       }
     }
   }
@@ -459,15 +596,22 @@ __global__ void k_copy_out(const void* in, double2* out, int64_t n) {
 
 template <bool F64>
 void internal_launch(Ctx& c, const void* H, void* e, void* j, void* g, hipStream_t s) {
-  unsigned long long* st = c.record ? c.d_stamps.as<unsigned long long>() : nullptr;
-  hipLaunchKernelGGL(k_internal<F64>, dim3(unsigned(c.slots)), dim3(256), 0, s, c.d_hi.as<float2>(),
-                     c.d_lo.as<float2>(), c.d_blocks.as<BlockDev>(), c.d_tiles.as<int4>(),
-                     c.d_slot_start.as<int32_t>(), H, e, j, g, st);
+  unsigned long long* st = c.record || c.gprof_on ? c.d_stamps.as<unsigned long long>() : nullptr;
+  auto go = [&](auto kern) {
+    hipLaunchKernelGGL(kern, dim3(unsigned(c.slots)), dim3(256), 0, s, c.d_hi.as<float2>(), c.d_lo.as<float2>(),
+                       c.d_blocks.as<BlockDev>(), c.d_tiles.as<int4>(), c.d_slot_start.as<int32_t>(), H, e, j, g, st);
+  };
+  if (F64) go(k_internal<true, 4>);
+  else if (c.rw_mixed == 4) go(k_internal<false, 4>);
+  else go(k_internal<false, 8>);
   SLIM_HIP(hipGetLastError());
 }
 
+// ext_e, ext_j: the internal part's e = Z H and j = H - M H (precision of the path)
+// computed elsewhere; the product then runs only its external part on them.
 template <bool F64>
-void matvec_t(Ctx& c, const void* x, void* y, void* e_out, void* g_out, void* a_out, void* phi_out, hipStream_t s) {
+void matvec_t(Ctx& c, const void* x, void* y, void* e_out, void* g_out, void* a_out, void* phi_out, hipStream_t s,
+              void* ext_e = nullptr, void* ext_j = nullptr) {
   const RWGTable& r = c.rwg;
   const int64_t ne = r.n_e, nt = r.n_t, nsys = ne + nt;
   const size_t es = F64 ? 16 : 8;
@@ -510,17 +654,21 @@ void matvec_t(Ctx& c, const void* x, void* y, void* e_out, void* g_out, void* a_
     SLIM_HIP(hipEventRecord(c.ev_join, c.s_phi));
   }
   // A1 + A2
-  mark(0);
-  internal_launch<F64>(c, X, c.d_e.p, c.d_j.p, g_out ? c.d_g.p : nullptr, s);
-  mark(0);
+  void* ev = ext_e ? ext_e : c.d_e.p;
+  void* jv = ext_j ? ext_j : c.d_j.p;
+  if (!ext_e) {
+    mark(0);
+    internal_launch<F64>(c, X, ev, jv, g_out ? c.d_g.p : nullptr, s);
+    mark(0);
+  }
   if (c.plain) {
     hipLaunchKernelGGL(k_dense_gemv<F64>, dim3(nblk(nt, 4)), dim3(256), 0, s, c.d_Lphi_hi.as<float2>(),
                        c.d_Lphi_lo.as<float2>(), nt, rho, c.d_area.as<double>(), c.d_phi.p);
     hipLaunchKernelGGL(k_dense_gemv<F64>, dim3(nblk(ne, 4)), dim3(256), 0, s, c.d_LA_hi.as<float2>(),
-                       c.d_LA_lo.as<float2>(), ne, c.d_j.p, nullptr, c.d_a.p);
+                       c.d_LA_lo.as<float2>(), ne, jv, nullptr, c.d_a.p);
     SLIM_HIP(hipGetLastError());
     hipLaunchKernelGGL((k_rows_A<F64, false>), dim3(nblk(ne, 4)), dim3(256), 0, s, nullptr, nullptr, nullptr,
-                       int64_t(0), 0, 0, nullptr, nullptr, nullptr, nullptr, c.d_a.p, c.d_phi.p, c.d_e.p,
+                       int64_t(0), 0, 0, nullptr, nullptr, nullptr, nullptr, c.d_a.p, c.d_phi.p, ev,
                        c.d_tplus.as<int32_t>(), c.d_tminus.as<int32_t>(), c.d_len.as<double>(),
                        c.d_ix_col.as<int32_t>(), c.d_ix_val.as<double>(), c.k0, inv_eta0, nullptr, Y, ne);
   } else {
@@ -529,7 +677,7 @@ void matvec_t(Ctx& c, const void* x, void* y, void* e_out, void* g_out, void* a_
                        c.d_pe_node.as<int32_t>(), c.d_pe_ptr.as<int32_t>(), c.d_pe_idx.as<int32_t>(),
                        F64 ? c.d_pe_w64.p : c.d_pe_w32.p, c.n_pe_nodes, c.d_pt_node.as<int32_t>(),
                        c.d_pt_ptr.as<int32_t>(), c.d_pt_idx.as<int32_t>(), F64 ? c.d_pt_w64.p : c.d_pt_w32.p,
-                       overlap ? int64_t(0) : c.n_pt_nodes, c.d_j.p, rho, oct_in, N3);
+                       overlap ? int64_t(0) : c.n_pt_nodes, jv, rho, oct_in, N3);
     SLIM_HIP(hipGetLastError());
     mark(1);
     mark(2);
@@ -548,15 +696,15 @@ void matvec_t(Ctx& c, const void* x, void* y, void* e_out, void* g_out, void* a_
     mark(4);
     hipLaunchKernelGGL((k_rows_A<F64, true>), dim3(nblk(ne, 4)), dim3(256), 0, s, c.d_we_base.as<int32_t>(),
                        F64 ? c.d_we_w64.p : c.d_we_w32.p, c.d_oct_out.p, N3, Nx, NxNy, c.d_nA_ptr.as<int64_t>(),
-                       c.d_nA_col.as<int32_t>(), F64 ? c.d_nA_v128.p : c.d_nA_v64.p, c.d_j.p, nullptr, c.d_phi.p,
-                       c.d_e.p, c.d_tplus.as<int32_t>(), c.d_tminus.as<int32_t>(), c.d_len.as<double>(),
+                       c.d_nA_col.as<int32_t>(), F64 ? c.d_nA_v128.p : c.d_nA_v64.p, jv, nullptr, c.d_phi.p,
+                       ev, c.d_tplus.as<int32_t>(), c.d_tminus.as<int32_t>(), c.d_len.as<double>(),
                        c.d_ix_col.as<int32_t>(), c.d_ix_val.as<double>(), c.k0, inv_eta0, c.d_a.p, Y, ne);
     mark(4);
   }
   SLIM_HIP(hipGetLastError());
   mark(5);
   hipLaunchKernelGGL(k_rows_T<F64>, dim3(nblk(nt)), dim3(256), 0, s, c.d_tri_edge.as<int32_t>(),
-                     c.d_tri_sign.as<int8_t>(), c.d_len.as<double>(), c.d_area.as<double>(), c.d_j.p, rho, c.k0,
+                     c.d_tri_sign.as<int8_t>(), c.d_len.as<double>(), c.d_area.as<double>(), jv, rho, c.k0,
                      Y + ne, nt);
   SLIM_HIP(hipGetLastError());
   mark(5);
@@ -565,7 +713,7 @@ void matvec_t(Ctx& c, const void* x, void* y, void* e_out, void* g_out, void* a_
     hipLaunchKernelGGL(k_copy_out<F64>, dim3(nblk(n)), dim3(256), 0, s, src, reinterpret_cast<double2*>(dst), n);
     SLIM_HIP(hipGetLastError());
   };
-  out(c.d_e.p, e_out, ne);
+  out(ev, e_out, ne);
   out(c.d_g.p, g_out, ne);
   out(c.d_a.p, a_out, ne);
   out(c.d_phi.p, phi_out, nt);
@@ -649,7 +797,34 @@ void matvec_graph(Ctx& c, slim_prec prec, const void* x, void* y, hipStream_t s)
     if (c.graphs.size() >= 8) c.drop_graphs();
     c.graphs.push_back({Ctx::GraphKey{int(prec), x, y}, exec});
   }
+  if (!c.gprof_on) {
+    SLIM_HIP(hipGraphLaunch(exec, s));
+    return;
+  }
+  // graph-path timing: the replay between two events on the caller's stream; the
+  // internal kernel from its own per-tile wall-clock stamps (first start to last end
+  // over all workgroups), which the captured launch writes; synchronous
+  SLIM_HIP(hipEventRecord(c.gev[0], s));
   SLIM_HIP(hipGraphLaunch(exec, s));
+  SLIM_HIP(hipEventRecord(c.gev[1], s));
+  SLIM_HIP(hipEventSynchronize(c.gev[1]));
+  float t_all = 0.f;
+  SLIM_HIP(hipEventElapsedTime(&t_all, c.gev[0], c.gev[1]));
+  std::vector<unsigned long long> st(2 * c.tiles.size());
+  SLIM_HIP(hipMemcpy(st.data(), c.d_stamps.p, st.size() * 8, hipMemcpyDeviceToHost));
+  unsigned long long t0 = ~0ull, t1 = 0;
+  for (size_t k = 0; k < c.tiles.size(); ++k) {
+    t0 = std::min(t0, st[2 * k]);
+    t1 = std::max(t1, st[2 * k + 1]);
+  }
+  if (c.wall_khz <= 0) {
+    int khz = 0;
+    SLIM_HIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, c.device));
+    c.wall_khz = khz;
+  }
+  c.gprof_ms[0] += t1 > t0 && c.wall_khz > 0 ? double(t1 - t0) / double(c.wall_khz) : 0.0;
+  c.gprof_ms[1] += t_all;
+  c.gprof_calls++;
 }
 
 // ms per mixed product on the library's stream, through the path slim_matvec
@@ -702,6 +877,68 @@ void matvec(Ctx& c, slim_prec prec, const void* x, void* y, void* e_out, void* g
             hipStream_t s) {
   if (prec == SLIM_FP64) matvec_t<true>(c, x, y, e_out, g_out, a_out, phi_out, s);
   else matvec_t<false>(c, x, y, e_out, g_out, a_out, phi_out, s);
+}
+
+// Y = A X for n_rhs columns.  MIXED: one split-BF16 MFMA launch of the internal blocks
+// per 64 columns, then the external part column by column on the columns' e and j.
+// FP64: every column through the single-column FP64 path (eager).
+void matvec_block(Ctx& c, slim_prec prec, const void* X, void* Y, int R, hipStream_t s) {
+  const int64_t ne = c.rwg.n_e, nsys = c.rwg.n_e + c.rwg.n_t;
+  const char* Xc = reinterpret_cast<const char*>(X);
+  char* Yc = reinterpret_cast<char*>(Y);
+  if (prec == SLIM_FP64) {
+    for (int col = 0; col < R; ++col)
+      matvec_t<true>(c, Xc + size_t(col) * nsys * 16, Yc + size_t(col) * nsys * 16, nullptr, nullptr, nullptr, nullptr, s);
+    return;
+  }
+  const int Rpad = (R + 15) & ~15;
+  if (c.blk_ldh == 0) {
+    // aligned H slices: block i occupies round_up(n_i, 8) + 32 entries of a plane column
+    std::vector<int64_t> hoff(c.blocks.size());
+    std::vector<int32_t> hpos(ne);
+    int64_t o = 0;
+    for (size_t i = 0; i < c.blocks.size(); ++i) {
+      hoff[i] = o;
+      for (int k = 0; k < c.blocks[i].n; ++k) hpos[c.blocks[i].e0 + k] = int32_t(o + k);
+      o += ((c.blocks[i].n + 7) & ~7) + 32;
+    }
+    SLIM_REQUIRE(o < (int64_t(1) << 31), SLIM_E_UNSUPPORTED, "too many unknowns for the block product");
+    c.d_blk_hoff.upload(hoff);
+    c.d_blk_hpos.upload(hpos);
+    c.blk_ldh = o;
+  }
+  if (c.blk_cols < Rpad) {
+    c.d_blk_hs.alloc(size_t(4) * Rpad * c.blk_ldh * 2);
+    SLIM_HIP(hipMemsetAsync(c.d_blk_hs.p, 0, c.d_blk_hs.bytes, s));
+    c.d_blk_h64.alloc(size_t(Rpad) * ne * 8);
+    c.d_blk_e.alloc(size_t(Rpad) * ne * 8);
+    c.d_blk_j.alloc(size_t(Rpad) * ne * 8);
+    c.blk_cols = Rpad;
+  }
+  const int64_t plane = int64_t(c.blk_cols) * c.blk_ldh;
+  __bf16* Hs = c.d_blk_hs.as<__bf16>();
+  hipLaunchKernelGGL(k_split_h, dim3(nblk(int64_t(R) * ne)), dim3(256), 0, s, reinterpret_cast<const double2*>(X), nsys,
+                     ne, R, c.blk_ldh, plane, c.d_blk_hpos.as<int32_t>(), c.d_blk_h64.as<float2>(), Hs);
+  SLIM_HIP(hipGetLastError());
+  if (c.prof_on) c.prof_mark(0, s);
+  for (int col0 = 0; col0 < R; col0 += 64) {
+    const int ncol = std::min(64, R - col0), ncg = (ncol + 15) / 16;
+    auto go = [&](auto kern) {
+      hipLaunchKernelGGL(kern, dim3(unsigned(c.slots)), dim3(256), 0, s, c.d_hi.as<float2>(), c.d_blocks.as<BlockDev>(),
+                         c.d_tiles.as<int4>(), c.d_slot_start.as<int32_t>(), c.d_blk_hoff.as<int64_t>(),
+                         Hs + int64_t(col0) * c.blk_ldh, plane, c.blk_ldh, c.d_blk_h64.as<float2>() + int64_t(col0) * ne,
+                         ne, ncol, c.d_blk_e.as<float2>() + int64_t(col0) * ne, c.d_blk_j.as<float2>() + int64_t(col0) * ne);
+    };
+    if (ncg == 1) go(k_internal_mfma<1>);
+    else if (ncg == 2) go(k_internal_mfma<2>);
+    else if (ncg == 3) go(k_internal_mfma<3>);
+    else go(k_internal_mfma<4>);
+    SLIM_HIP(hipGetLastError());
+  }
+  if (c.prof_on) c.prof_mark(0, s);
+  for (int col = 0; col < R; ++col)
+    matvec_t<false>(c, Xc + size_t(col) * nsys * 16, Yc + size_t(col) * nsys * 16, nullptr, nullptr, nullptr, nullptr, s,
+                    c.d_blk_e.as<float2>() + int64_t(col) * ne, c.d_blk_j.as<float2>() + int64_t(col) * ne);
 }
 
 // Internal part alone: H (complex128) -> e = Z H, g = M H (complex128 outputs).

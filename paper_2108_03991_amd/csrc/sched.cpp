@@ -49,13 +49,14 @@ void pack_tiles(Ctx& c, int mode) {
       c.tiles.insert(c.tiles.end(), q[s].begin(), q[s].end());
     }
   } else {
-    // moldable step: P_i panels per block so that each panel costs <= ideal/4
+    // moldable step: P_i panels per block so that each panel costs <= ideal/4; panel
+    // heights are whole 16-row groups (the row tile of the matrix-core kernel)
     for (int i = 0; i < nb; ++i) {
       const int n = c.blocks[i].n, ld = (n + 1) & ~1, rows = 2 * n;
       double w = double(rows) * ld;
       int64_t P = std::max<int64_t>(1, int64_t(std::ceil(w / (0.25 * ideal))));
-      int R = int(std::min<int64_t>(rows, std::max<int64_t>(4, (rows + P - 1) / P)));
-      R = std::min(rows, ((R + 3) / 4) * 4);
+      int R = int(std::min<int64_t>(rows, std::max<int64_t>(16, (rows + P - 1) / P)));
+      R = std::min(rows, ((R + 15) / 16) * 16);
       for (int r0 = 0; r0 < rows; r0 += R) {
         const int rr = std::min(R, rows - r0);
         double cost = double((rr + 7) / 8 * 8) * double((ld + 255) / 256 * 256);

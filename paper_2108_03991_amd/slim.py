@@ -33,7 +33,8 @@ class BuildOpts(C.Structure):
                 ("tile_rows", C.c_int32), ("internal_kernel", C.c_int32), ("slots", C.c_int32),
                 ("mem_budget", C.c_int64), ("verbose", C.c_int32), ("use_graphs", C.c_int32),
                 ("precond", C.c_int32), ("precond_overlap", C.c_int32), ("precond_cap", C.c_int64),
-                ("precond_budget", C.c_int64)]
+                ("precond_budget", C.c_int64), ("fft_zblock", C.c_int32), ("rows_per_wave", C.c_int32),
+                ("tune_cache", C.c_char_p)]
 
 
 class Layout(C.Structure):
@@ -42,7 +43,8 @@ class Layout(C.Structure):
                 ("nnz_near_A", C.c_int64), ("nnz_near_phi", C.c_int64), ("internal_entries", C.c_int64),
                 ("n_tiles", C.c_int64), ("slots", C.c_int32), ("tile_rows", C.c_int32), ("mean_edge", C.c_double),
                 ("build_seconds", C.c_double), ("device_bytes", C.c_int64), ("precond_blocks", C.c_int64),
-                ("precond_entries", C.c_int64), ("precond_cap", C.c_int64)]
+                ("precond_entries", C.c_int64), ("precond_cap", C.c_int64), ("fft_zblock", C.c_int32),
+                ("rows_per_wave", C.c_int32)]
 
 
 class SolveOpts(C.Structure):
@@ -54,6 +56,21 @@ class SolveInfo(C.Structure):
     _fields_ = [("iterations", C.c_int32), ("outer_steps", C.c_int32), ("rel_residual", C.c_double),
                 ("seconds", C.c_double), ("matvec_seconds", C.c_double), ("n_matvec_fp64", C.c_int32),
                 ("n_matvec_mixed", C.c_int32), ("n_precond", C.c_int32)]
+
+
+class Port(C.Structure):
+    _fields_ = [("obj", C.c_int32), ("point", C.c_double * 3), ("axis", C.c_double * 3), ("radius", C.c_double)]
+
+
+def _ports(ports):
+    """(obj, point, axis, radius) tuples -> a ctypes array of slim_port."""
+    arr = (Port * len(ports))()
+    for k, (obj, point, axis, radius) in enumerate(ports):
+        arr[k].obj = int(obj)
+        arr[k].point[:] = [float(v) for v in point]
+        arr[k].axis[:] = [float(v) for v in axis]
+        arr[k].radius = float(radius)
+    return arr
 
 
 class Material(C.Structure):
@@ -121,13 +138,17 @@ def lib():
         L.slim_layered_gammas.argtypes = [C.POINTER(Medium), C.c_double, i64, dp, dp]
         L.slim_profile.argtypes = [vp, i32]
         L.slim_profile_read.argtypes = [vp, dp, C.POINTER(i64)]
+        L.slim_matvec_block.argtypes = [vp, i32, vp, vp, i32, vp]
+        L.slim_rhs_ports.argtypes = [vp, C.POINTER(Port), i32, vp, vp]
+        L.slim_port_currents.argtypes = [vp, C.POINTER(Port), i32, vp, i32, dp, vp]
         for name in ("slim_create", "slim_set_mesh", "slim_set_materials", "slim_build", "slim_get_layout",
                      "slim_get_rwg", "slim_matvec", "slim_matvec_parts", "slim_internal_apply",
                      "slim_rhs_planewave", "slim_solve", "slim_sched_record", "slim_sched_tiles",
                      "slim_sched_train", "slim_sched_set_mode", "slim_mlp_forward_backward", "slim_profile",
                      "slim_profile_read", "slim_aim_convolve", "slim_get_aim", "slim_get_near",
                      "slim_precond_apply", "slim_get_precond", "slim_precond_partition", "slim_set_medium",
-                     "slim_aim_convolve_layered", "slim_get_layered_kernels", "slim_layered_gammas"):
+                     "slim_aim_convolve_layered", "slim_get_layered_kernels", "slim_layered_gammas",
+                     "slim_matvec_block", "slim_rhs_ports", "slim_port_currents"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -139,7 +160,8 @@ EXPORTS = ["slim_default_build_opts", "slim_create", "slim_destroy", "slim_last_
            "slim_sched_tiles", "slim_sched_train", "slim_sched_set_mode", "slim_mlp_forward_backward",
            "slim_profile", "slim_profile_read", "slim_aim_convolve", "slim_get_aim", "slim_get_near",
            "slim_precond_apply", "slim_get_precond", "slim_precond_partition", "slim_set_medium",
-           "slim_aim_convolve_layered", "slim_get_layered_kernels", "slim_layered_gammas"]
+           "slim_aim_convolve_layered", "slim_get_layered_kernels", "slim_layered_gammas", "slim_matvec_block",
+           "slim_rhs_ports", "slim_port_currents"]
 
 
 def _ptr(t):
@@ -162,6 +184,8 @@ def default_build_opts(**kw):
     for k, v in kw.items():
         if k == "grid":
             o.grid[0], o.grid[1], o.grid[2] = (int(x) for x in v)
+        elif k == "tune_cache":
+            o.tune_cache = None if v is None else os.fsencode(v)
         else:
             setattr(o, k, v)
     return o
@@ -259,6 +283,23 @@ class Context:
         self._check(lib().slim_matvec_parts(self._h, prec, _ptr(x), _ptr(y), _ptr(e), _ptr(g), _ptr(a), _ptr(phi),
                                             _stream(stream)))
 
+    def matvec_block(self, prec, X, Y, n_rhs, stream=None):
+        """Y = A X for n_rhs columns (column-major n_sys x n_rhs complex128 device arrays)."""
+        self._check(lib().slim_matvec_block(self._h, prec, _ptr(X), _ptr(Y), int(n_rhs), _stream(stream)))
+
+    def rhs_ports(self, ports, B, stream=None):
+        """Unit-voltage lumped-port right-hand sides, one column of B per (obj, point, axis, radius)."""
+        arr = _ports(ports)
+        self._check(lib().slim_rhs_ports(self._h, arr, len(ports), _ptr(B), _stream(stream)))
+
+    def port_currents(self, ports, X, n_rhs, stream=None):
+        """Port currents (n_ports x n_rhs complex) of the solution columns X."""
+        arr = _ports(ports)
+        out = np.zeros(2 * len(ports) * int(n_rhs))
+        self._check(lib().slim_port_currents(self._h, arr, len(ports), _ptr(X), int(n_rhs),
+                                             out.ctypes.data_as(C.POINTER(C.c_double)), _stream(stream)))
+        return out.view(np.complex128).reshape(int(n_rhs), len(ports)).T
+
     def internal_apply(self, prec, H, e=None, g=None, timed=False, stream=None):
         ms = C.c_double(0.0)
         self._check(lib().slim_internal_apply(self._h, prec, _ptr(H), _ptr(e), _ptr(g),
@@ -329,7 +370,8 @@ class Context:
         return ptr, col, val.view(np.complex128)
 
     def profile(self, on=True):
-        self._check(lib().slim_profile(self._h, int(bool(on))))
+        """on: False/0 stop, True/1 staged per-stage events, 2 graph-path events (see slim.h)."""
+        self._check(lib().slim_profile(self._h, int(on)))
 
     def profile_read(self):
         ms = (C.c_double * 6)()

@@ -133,3 +133,24 @@ def test_layered_errors():
     with pytest.raises(slim.SlimError) as ei:
         plain.set_medium(-1.0, [], "pec")
     assert ei.value.code == 3
+
+
+def test_layered_convolution_tall_z_sampled():
+    """Nz = 128: the layered z step runs length-256 passes and the spectrum product over
+    129 kz pairs.  The oracle's brute-force layered sum is taken at 50 sampled target
+    nodes (first and last included), each summed over every source node."""
+    import torch
+    from oracle.aim import convolve_layered_direct
+    N = (8, 8, 128)
+    ctx, grid, st = _setup(N)
+    n3 = grid.n_nodes
+    src = random_complex(4 * n3, 22)
+    rng = np.random.default_rng(1)
+    tg = np.union1d(rng.choice(n3, 48, replace=False), [0, n3 - 1])
+    ref = convolve_layered_direct(grid, FREQ, st, src.reshape(4, n3), targets=tg)
+    dst = torch.zeros(4 * n3, dtype=torch.complex128, device='cuda')
+    for prec, tol in ((FP64, 1e-9), (MIXED, 1e-5)):
+        ctx.aim_convolve_layered(prec, torch.tensor(src, device='cuda'), dst)
+        got = dst.cpu().numpy().reshape(4, n3)[:, tg]
+        for c in range(4):
+            assert rel(got[c], ref[c]) <= tol, (prec, c, rel(got[c], ref[c]))

@@ -43,3 +43,39 @@ def test_trained_cost_model_packing():
     print("makespan ms naive %.3f lpt %.3f mlp %.3f (gain of the trained model over LPT %.1f %%)"
           % (times[2], times[0], times[1], 100 * (times[0] / times[1] - 1)))
     assert times[1] <= times[0] * 1.05      # the learned packing does not lose to LPT on flop counts
+
+
+def test_lpt_packer_matches_alg1():
+    """The library's LPT packing (mode 0) against the oracle's Alg. 1 on the same task costs:
+    the same processor (slot) for every task, in the same order, and the same makespan.
+    The task costs are the kernel-shaped flop estimate of the library (rows rounded up to
+    the eight-row sweep, row length up to the 256-column chunk); both sides break ties on
+    the lowest slot index and keep equal costs in task order.  The makespan also obeys
+    the LPT bound (13) against the lower bound max(sum W / P, max W) of the optimum, and
+    no panel carries more than a quarter of the ideal per-slot load, up to the 16-row
+    granule that panel heights are rounded to (the moldable split)."""
+    from oracle.sched import lpt, lpt_bound
+    m = conductors_c5(seed=3, n_obj=160)
+    ctx, lay = context(m, freq=5e9, grid=(0, 0, 0), slots=64, precond=0)
+    tiles = ctx.sched_tiles()[:, :5].astype(np.int64)        # block, row0, rows, n, slot (queue order)
+    order = np.lexsort((tiles[:, 1], tiles[:, 0]))          # generation order: block, then row0
+    t = tiles[order]
+    ld = (t[:, 3] + 1) & ~1
+    tau = [float(v) for v in ((t[:, 2] + 7) // 8 * 8) * ((ld + 255) // 256 * 256)]
+    C, cmax = lpt(tau, lay.slots)
+    slot_of = np.empty(len(tau), dtype=np.int64)
+    for p, tasks in enumerate(C):
+        slot_of[tasks] = p
+    assert np.array_equal(slot_of, t[:, 4])
+    # the order inside every queue is the order of assignment
+    pos = {int(k): i for i, k in enumerate(order)}
+    for p in range(lay.slots):
+        q = [pos[k] for k in np.nonzero(tiles[:, 4] == p)[0]]
+        assert q == C[p]
+    F = np.zeros(lay.slots)
+    np.add.at(F, t[:, 4], tau)
+    assert F.max() == cmax
+    assert cmax <= lpt_bound(lay.slots) * max(sum(tau) / lay.slots, max(tau)) * 1.0000001
+    ideal = float(np.sum(t[:, 2] * ld)) / lay.slots
+    for rows, l in zip(t[:, 2], ld):
+        assert rows * l <= 0.25 * ideal + 16 * l
