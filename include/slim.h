@@ -407,6 +407,20 @@ slim_status slim_mlp_forward_backward(int32_t F, int32_t B, const float* params_
                                       const float* X_dev, const float* t_dev, float* y_dev,
                                       float* grad_dev, float* loss_dev, void* stream);
 
+/* Allocation-free variant of slim_mlp_forward_backward, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight training loops,
+ * harnesses that forbid hipMalloc).  Same arguments, layout and results (the
+ * same kernels); it allocates nothing and only enqueues on `stream` (no
+ * synchronization).  Its workspace, the per-wave partial gradients and losses,
+ * is one static device array per GPU of about 9.8 MB, held until the process
+ * ends, which limits B to 32768 samples (SLIM_E_ARG beyond, nothing launched).
+ * Every call on a GPU uses that GPU's one workspace: calls that overlap on the
+ * same GPU (different streams, threads) race and must be serialized by the
+ * caller.  The workspace needs no clearing between calls.                     */
+slim_status slim_mlp_forward_backward_noalloc(int32_t F, int32_t B, const float* params_dev, const float* X_dev,
+                                              const float* t_dev, float* y_dev, float* grad_dev, float* loss_dev,
+                                              void* stream);
+
 #ifdef __cplusplus
 }
 #endif

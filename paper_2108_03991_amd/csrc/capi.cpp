@@ -74,6 +74,12 @@ slim_status slim_create(int32_t hip_device, slim_ctx** out) {
       delete h;
       return SLIM_E_HIP;
     }
+    // set-up of the allocation-free entry point's workspace on this device (the
+    // entry point looks it up itself on a device no context was created on)
+    try {
+      (void)noalloc_workspace();
+    } catch (const Error&) {
+    }
     *out = h;
     return SLIM_OK;
   } catch (...) {

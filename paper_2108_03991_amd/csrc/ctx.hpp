@@ -196,6 +196,8 @@ void layered_gammas(const slim_medium& m, double freq, int64_t n, const double* 
 void port_ring(const Ctx& c, const slim_port& p, std::vector<int32_t>& edges, std::vector<double>& w);
 void port_currents(Ctx& c, const std::vector<int32_t>& edges, const std::vector<double>& w,
                    const std::vector<int32_t>& start, const void* X, int n_rhs, double* I, hipStream_t s);
+// mlp.hip: device address of the allocation-free entry point's workspace on the current device
+float* noalloc_workspace();
 // sched.cpp
 void pack_tiles(Ctx& c, int mode);
 // precond.hip

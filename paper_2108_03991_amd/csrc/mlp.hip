@@ -10,6 +10,7 @@
 //   (size = square root of the surface area), log rows, (n_i mod 64)/64,
 // standardised; target: log(tile time).  Loss: mean squared error.
 #include <algorithm>
+#include <mutex>
 
 #include "ctx.hpp"
 
@@ -127,16 +128,59 @@ __global__ void k_adam(int np, float* p, const float* g, float* m, float* v, flo
   p[i] -= lr * (m[i] / c1) / (sqrtf(v[i] / c2) + eps);
 }
 
+// Forward/backward on workspace the caller provides: partial (nw x n_params(F) floats)
+// and ploss (nw floats), nw = ceil(B / 64).  Every entry of both is written before
+// it is read, so the workspace needs no clearing.
+void fb_launch_ws(int F, int B, const float* p, const float* X, const float* t, float* y, float* grad, float* loss,
+                  float* partial, float* ploss, hipStream_t s) {
+  const int nw = (B + 63) / 64, np = n_params(F);
+  hipLaunchKernelGGL(k_mlp_fb, dim3(nw), dim3(64), 0, s, F, B, p, X, t, y, partial, ploss);
+  hipLaunchKernelGGL(k_mlp_reduce, dim3((np + 255) / 256), dim3(256), 0, s, np, nw, B, partial, ploss, grad, loss);
+  SLIM_HIP(hipGetLastError());
+}
+
 void fb_launch(int F, int B, const float* p, const float* X, const float* t, float* y, float* grad, float* loss,
                DevBuf& partial, DevBuf& ploss, hipStream_t s) {
   const int nw = (B + 63) / 64, np = n_params(F);
   if (partial.bytes < size_t(nw) * np * 4) partial.alloc(size_t(nw) * np * 4);
   if (ploss.bytes < size_t(nw) * 4) ploss.alloc(size_t(nw) * 4);
-  hipLaunchKernelGGL(k_mlp_fb, dim3(nw), dim3(64), 0, s, F, B, p, X, t, y, partial.as<float>(), ploss.as<float>());
-  hipLaunchKernelGGL(k_mlp_reduce, dim3((np + 255) / 256), dim3(256), 0, s, np, nw, B, partial.as<float>(),
-                     ploss.as<float>(), grad, loss);
-  SLIM_HIP(hipGetLastError());
+  fb_launch_ws(F, B, p, X, t, y, grad, loss, partial.as<float>(), ploss.as<float>(), s);
 }
+
+// ---- workspace of the allocation-free entry point ---------------------------
+// One static device array per GPU, held until the process ends: the per-wave
+// partial gradients (kNoAllocWaves x n_params(FMAX)) followed by the per-wave
+// partial losses.  In host code `scratch` is only a symbol; its device address
+// comes from hipGetSymbolAddress, once per device (noalloc_workspace).
+constexpr int kNoAllocMaxB = 32768;
+constexpr int kNoAllocWaves = kNoAllocMaxB / 64;
+constexpr size_t kScratchFloats = size_t(kNoAllocWaves) * (HID * FMAX + HID + HID * HID + HID + HID + 1) + kNoAllocWaves;
+static_assert(kScratchFloats * 4 < (size_t(12) << 20), "workspace of the allocation-free entry point stays modest");
+
+constexpr int kMaxDevices = 64;
+std::mutex g_ws_mutex;
+float* g_ws_ptr[kMaxDevices] = {};
+
+}  // namespace
+
+static __device__ __align__(256) float scratch[kScratchFloats];
+
+// Device address of `scratch` on the current device (looked up once per device).
+float* noalloc_workspace() {
+  int dev = -1;
+  SLIM_HIP(hipGetDevice(&dev));
+  SLIM_REQUIRE(dev >= 0 && dev < kMaxDevices, SLIM_E_UNSUPPORTED, "device index beyond the workspace table");
+  std::lock_guard<std::mutex> lock(g_ws_mutex);
+  if (!g_ws_ptr[dev]) {
+    void* ptr = nullptr;
+    SLIM_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    SLIM_REQUIRE(ptr != nullptr, SLIM_E_HIP, "hipGetSymbolAddress returned no address for the workspace");
+    g_ws_ptr[dev] = static_cast<float*>(ptr);
+  }
+  return g_ws_ptr[dev];
+}
+
+namespace {
 
 }  // namespace
 
@@ -278,6 +322,21 @@ slim_status slim_mlp_forward_backward(int32_t F, int32_t B, const float* params,
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     fb_launch(F, B, params, X, t, y, grad, loss, part, pl, s);
     SLIM_HIP(hipStreamSynchronize(s));
+    return SLIM_OK;
+  } catch (const Error& e) {
+    return e.code;
+  } catch (...) {
+    return SLIM_E_HIP;
+  }
+}
+
+slim_status slim_mlp_forward_backward_noalloc(int32_t F, int32_t B, const float* params, const float* X,
+                                              const float* t, float* y, float* grad, float* loss, void* stream) {
+  if (F < 1 || F > FMAX || B < 1 || B > kNoAllocMaxB || !params || !X || !t || !y || !grad) return SLIM_E_ARG;
+  try {
+    float* ws = noalloc_workspace();
+    fb_launch_ws(F, B, params, X, t, y, grad, loss, ws, ws + size_t(kNoAllocWaves) * n_params(FMAX),
+                 reinterpret_cast<hipStream_t>(stream));
     return SLIM_OK;
   } catch (const Error& e) {
     return e.code;

@@ -126,6 +126,7 @@ def lib():
         L.slim_sched_train.argtypes = [vp, i32, C.c_double, dp]
         L.slim_sched_set_mode.argtypes = [vp, i32]
         L.slim_mlp_forward_backward.argtypes = [i32, i32, vp, vp, vp, vp, vp, vp, vp]
+        L.slim_mlp_forward_backward_noalloc.argtypes = [i32, i32, vp, vp, vp, vp, vp, vp, vp]
         L.slim_aim_convolve.argtypes = [vp, i32, vp, vp, i32, vp]
         L.slim_get_aim.argtypes = [vp, vp, vp, vp, vp]
         L.slim_get_near.argtypes = [vp, i32, vp, vp, vp]
@@ -148,7 +149,8 @@ def lib():
                      "slim_profile_read", "slim_aim_convolve", "slim_get_aim", "slim_get_near",
                      "slim_precond_apply", "slim_get_precond", "slim_precond_partition", "slim_set_medium",
                      "slim_aim_convolve_layered", "slim_get_layered_kernels", "slim_layered_gammas",
-                     "slim_matvec_block", "slim_rhs_ports", "slim_port_currents"):
+                     "slim_matvec_block", "slim_rhs_ports", "slim_port_currents",
+                     "slim_mlp_forward_backward_noalloc"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -161,7 +163,7 @@ EXPORTS = ["slim_default_build_opts", "slim_create", "slim_destroy", "slim_last_
            "slim_profile", "slim_profile_read", "slim_aim_convolve", "slim_get_aim", "slim_get_near",
            "slim_precond_apply", "slim_get_precond", "slim_precond_partition", "slim_set_medium",
            "slim_aim_convolve_layered", "slim_get_layered_kernels", "slim_layered_gammas", "slim_matvec_block",
-           "slim_rhs_ports", "slim_port_currents"]
+           "slim_rhs_ports", "slim_port_currents", "slim_mlp_forward_backward_noalloc"]
 
 
 def _ptr(t):
@@ -417,6 +419,14 @@ def precond_partition(verts, tris, obj, n_obj, cap, overlap):
     if st != 0:
         raise SlimError(st, "slim_precond_partition failed")
     return [(ei[ep[k]:ep[k + 1]].copy(), oi[op[k]:op[k + 1]].copy()) for k in range(nb.value)]
+
+
+def mlp_forward_backward_noalloc(F, B, params, X, t, y, grad, loss, stream=None):
+    """The allocation-free variant (enqueues only; B <= 32768; one workspace per GPU)."""
+    st = lib().slim_mlp_forward_backward_noalloc(int(F), int(B), _ptr(params), _ptr(X), _ptr(t), _ptr(y), _ptr(grad),
+                                                 _ptr(loss), _stream(stream))
+    if st != 0:
+        raise SlimError(st, "slim_mlp_forward_backward_noalloc failed")
 
 
 def mlp_forward_backward(F, B, params, X, t, y, grad, loss, stream=None):
