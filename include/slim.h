@@ -377,7 +377,7 @@ slim_status slim_precond_partition(const double* xyz, int64_t n_vert, const int3
  *   5 continuity rows and casts.
  * slim_profile(ctx, 2): the default path (captured graph, pulse path concurrent),
  *   with events around each replay on the caller's stream and the internal
- *   kernel's own wall-clock stamps (first tile start to last tile end) inside it;
+ *   kernel's own wall-clock stamps (first workgroup start to last workgroup end);
  *   every product then waits for its own end.  ms[0] = internal kernel inside the
  *   replays, ms[1] = whole replays.
  * slim_profile(ctx, 0) stops.  Each call clears the sums; slim_profile_read
@@ -395,6 +395,20 @@ slim_status slim_sched_tiles(slim_ctx* ctx, double* out, int64_t* n_tiles);
 /* Train the MLP cost model (on the GPU, own forward/backward kernels) on the
  * recorded tiles; returns the final training loss. */
 slim_status slim_sched_train(slim_ctx* ctx, int32_t epochs, double lr, double* final_loss);
+/* Training samples of the last recorded tiles, for training on other workloads:
+ * per tile 8 doubles, the seven raw (unstandardised) features of the cost model
+ * (log n_i, log aspect of the object's box, log(skin depth / sqrt(area)), log
+ * rows, (n_i mod 64) / 64, log of the row sweeps of the tile's busiest wave
+ * (rows / (4 x rows per wave), rounded up), log of the 256-column chunks of a
+ * row) and the log of the tile's duration in wall-clock ticks.  *n in: capacity
+ * (tiles), out: count; out may be NULL (count only).  SLIM_E_STATE without
+ * recorded timings. */
+slim_status slim_sched_export(slim_ctx* ctx, double* out, int64_t* n);
+/* Train the context's cost model on n samples in the slim_sched_export layout
+ * (for instance pooled from other workloads); features are standardised on
+ * these samples.  SLIM_E_ARG on non-finite samples. */
+slim_status slim_sched_train_data(slim_ctx* ctx, int64_t n, const double* samples, int32_t epochs, double lr,
+                                  double* final_loss);
 /* 0 = LPT on flop counts, 1 = MLP-predicted times, 2 = naive (object order,
  * round robin); re-packs the work queues and re-captures the graphs. */
 slim_status slim_sched_set_mode(slim_ctx* ctx, int32_t mode);

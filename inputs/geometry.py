@@ -229,7 +229,7 @@ def line_bundle_c3(seed=0, n_lines=200, a_tri=1.5e-12, n_y=20, n_z=10,
                    pitch_y=10 * UM, pitch_z=8 * UM):
     """200 parallel lines along x on a 20 x 10 lattice; lengths log-uniform 10-500 um."""
     rng = np.random.default_rng(seed)
-    parts = []
+    parts, lines = [], []
     for k in range(n_lines):
         l = math.exp(rng.uniform(math.log(10.0), math.log(500.0))) * UM
         w, h = rng.uniform(1.0, 4.0, size=2) * UM
@@ -237,10 +237,26 @@ def line_bundle_c3(seed=0, n_lines=200, a_tri=1.5e-12, n_y=20, n_z=10,
         t = int(np.clip(round(area / a_tri), 100, 5000))
         div = box_divisions((l, w, h), t)
         iy, iz = k % n_y, k // n_y
-        parts.append(box_mesh((0.0, iy * pitch_y, iz * pitch_z), (l, w, h), div))
+        origin = (0.0, iy * pitch_y, iz * pitch_z)
+        parts.append(box_mesh(origin, (l, w, h), div))
+        lines.append(dict(origin=origin, size=(l, w, h), div=div))
     m = merge(parts)
-    m.info = dict(workload="line_bundle", seed=seed)
+    m.info = dict(workload="line_bundle", seed=seed, lines=lines)
     return m
+
+
+def line_end_ports(mesh, lines):
+    """Lumped ports at both ends of the given lines of a line bundle: the vertex ring one
+    division in from each end, axis along the line (+x), as (obj, point, axis, radius)."""
+    out = []
+    for k in lines:
+        ln = mesh.info["lines"][k]
+        (x0, y0, z0), (l, w, h), (nx, _, _) = ln["origin"], ln["size"], ln["div"]
+        if nx < 2:
+            raise ValueError("line %d has no vertex ring inside it" % k)
+        for x in (x0 + l / nx, x0 + l * (nx - 1) / nx):
+            out.append((k, (x, y0 + w / 2, z0 + h / 2), (1.0, 0.0, 0.0), max(w, h)))
+    return out
 
 
 def conductors_c5(seed=0, n_obj=2000, scale=76.0, alpha=1.2, t_min=50, t_max=20000,

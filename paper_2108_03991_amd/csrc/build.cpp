@@ -172,10 +172,13 @@ Ctx::~Ctx() {
     for (hipEvent_t e : v) (void)hipEventDestroy(e);
   if (ev_fork) (void)hipEventDestroy(ev_fork);
   if (ev_join) (void)hipEventDestroy(ev_join);
+  if (ev_zfork) (void)hipEventDestroy(ev_zfork);
+  if (ev_zjoin) (void)hipEventDestroy(ev_zjoin);
   for (hipEvent_t e : gev)
     if (e) (void)hipEventDestroy(e);
   if (s_aux) (void)hipStreamDestroy(s_aux);
   if (s_phi) (void)hipStreamDestroy(s_phi);
+  if (s_int) (void)hipStreamDestroy(s_int);
 }
 
 static void build_internal(Ctx& c, hipStream_t s) {
@@ -360,7 +363,8 @@ static void autotune(Ctx& c, const slim_build_opts& o, hipStream_t s) {
     std::snprintf(arch, sizeof(arch), "%s", prop.gcnArchName);
     if (char* colon = std::strchr(arch, ':')) *colon = '\0';
   }
-  const int pack_mode = o.sched_mode == 1 ? 0 : o.sched_mode;
+  // before any training the learned modes pack on flop counts
+  const int pack_mode = o.sched_mode == 1 ? 0 : o.sched_mode == 4 ? 3 : o.sched_mode;
   const std::string key = tune_key(c, arch, cus);
   int per_cu = 0, zb = 0, rw = 0;
   if (tune_cache_lookup(o.tune_cache, key, per_cu, zb, rw)) {
@@ -500,7 +504,11 @@ void build_all(Ctx& c, const slim_build_opts& o) {
   if (!c.s_phi) SLIM_HIP(hipStreamCreateWithFlags(&c.s_phi, hipStreamNonBlocking));
   if (!c.ev_fork) SLIM_HIP(hipEventCreateWithFlags(&c.ev_fork, hipEventDisableTiming));
   if (!c.ev_join) SLIM_HIP(hipEventCreateWithFlags(&c.ev_join, hipEventDisableTiming));
+  if (!c.s_int) SLIM_HIP(hipStreamCreateWithFlags(&c.s_int, hipStreamNonBlocking));
+  if (!c.ev_zfork) SLIM_HIP(hipEventCreateWithFlags(&c.ev_zfork, hipEventDisableTiming));
+  if (!c.ev_zjoin) SLIM_HIP(hipEventCreateWithFlags(&c.ev_zjoin, hipEventDisableTiming));
 
+  SLIM_REQUIRE(o.sched_mode >= 0 && o.sched_mode <= 4, SLIM_E_ARG, "sched_mode must be 0..4");
   c.tile_rows = o.tile_rows > 0 ? o.tile_rows : 64;
   c.sched_mode = o.sched_mode;
   c.drop_graphs();

@@ -490,7 +490,7 @@ slim_status slim_profile(slim_ctx* h, int32_t on) {
     h->c.gprof_on = graph;
     for (auto& u : h->c.prof_used) u = 0;
     h->c.prof_calls = 0;
-    h->c.gprof_ms[0] = h->c.gprof_ms[1] = 0.0;
+    for (double& v : h->c.gprof_ms) v = 0.0;
     h->c.gprof_calls = 0;
     return SLIM_OK;
   });
@@ -501,8 +501,7 @@ slim_status slim_profile_read(slim_ctx* h, double* ms, int64_t* n_matvec) {
     SLIM_REQUIRE(ms, SLIM_E_ARG, "null output");
     if (h->c.gprof_on) {
       for (int st = 0; st < 6; ++st) ms[st] = 0.0;
-      ms[0] = h->c.gprof_ms[0];
-      ms[1] = h->c.gprof_ms[1];
+      for (int k = 0; k < 4; ++k) ms[k] = h->c.gprof_ms[k];
       if (n_matvec) *n_matvec = h->c.gprof_calls;
       return SLIM_OK;
     }
@@ -556,8 +555,8 @@ slim_status slim_sched_tiles(slim_ctx* h, double* out, int64_t* n_tiles) {
 slim_status slim_sched_set_mode(slim_ctx* h, int32_t mode) {
   return guard(h, [&]() {
     SLIM_REQUIRE(h->c.built, SLIM_E_STATE, "operator not built");
-    SLIM_REQUIRE(mode >= 0 && mode <= 2, SLIM_E_ARG, "unknown scheduling mode");
-    SLIM_REQUIRE(mode != 1 || !h->c.mlp_params.empty(), SLIM_E_STATE, "cost model not trained");
+    SLIM_REQUIRE(mode >= 0 && mode <= 4, SLIM_E_ARG, "unknown scheduling mode");
+    SLIM_REQUIRE((mode != 1 && mode != 4) || !h->c.mlp_params.empty(), SLIM_E_STATE, "cost model not trained");
     pack_tiles(h->c, mode);
     h->c.last_stamps.clear();
     h->c.layout.n_tiles = int64_t(h->c.tiles.size());

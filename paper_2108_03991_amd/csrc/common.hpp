@@ -66,6 +66,7 @@ struct DevBuf {
     hipError_t e = hipMalloc(&p, n);
     if (e != hipSuccess) {
       p = nullptr;
+      (void)hipGetLastError();   // a failed allocation must not surface at the next launch check
       throw Error(SLIM_E_OOM, "hipMalloc of " + std::to_string(n) + " bytes failed");
     }
     bytes = n;

@@ -64,13 +64,18 @@ struct Ctx {
   // ---- work queues of the persistent internal kernel ----
   std::vector<Tile> tiles;              // grouped by slot
   std::vector<int32_t> slot_start;      // slots+1
-  DevBuf d_tiles, d_slot_start;
+  DevBuf d_tiles, d_slot_start;         // slot_start: 2 x (slots + 1), one range table per phase
+  int32_t phase_first[2] = {0, 0};      // tiles of phase 0 (rows of M_i) and phase 1 (rows of Z_i)
+  int32_t phase_count[2] = {0, 0};
+  bool dynamic = false;                 // dynamic dispatch (scheduling modes 3 and 4)
+  DevBuf d_qctr;                        // dispatch counters: GEMV phases 0, 1; block product phases 0, 1
   int slots = 0;
   int tile_rows = 64;
   int rw_mixed = 8;                     // rows per wave of the mixed internal kernel (4 or 8)
   int sched_mode = 0;
   bool record = false;
   DevBuf d_stamps;                      // 2 x n_tiles uint64 timestamps
+  DevBuf d_span;                        // 2 phases x 2 x slots uint64: start and end of every workgroup (graph-path timing)
   std::vector<double> last_stamps;
 
   // ---- I_x (sparse: the other edges of T+ and T-), per RWG row ----
@@ -91,7 +96,8 @@ struct Ctx {
   // interpolation W = P^T (basis-major: base node + 27 weights per component)
   DevBuf d_we_base, d_we_w32, d_we_w64, d_wt_base, d_wt_w32, d_wt_w64;
   // Green's function spectrum on the (2N)^3 grid, scaled by 1/(2N)^3
-  DevBuf d_ghat64, d_ghat128;
+  DevBuf d_ghat64, d_ghat128;           // octant [kz][ky][kx]
+  DevBuf d_ghatz64, d_ghatz128;         // the same octant in the fused z pass's order [ky][kz][kx]
   DevBuf d_tw64, d_tw128;               // twiddles for each axis length
   // FFT work arrays (4 components)
   DevBuf d_oct_in, d_oct_in32;          // projected sources: complex128 / complex64 (zero off the occupied nodes)
@@ -140,6 +146,8 @@ struct Ctx {
   hipStream_t s_aux = nullptr;
   hipStream_t s_phi = nullptr;          // pulse (phi) path of the product, concurrent with the internal blocks
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  hipStream_t s_int = nullptr;          // rows of Z_i, concurrent with the projection and convolution of j
+  hipEvent_t ev_zfork = nullptr, ev_zjoin = nullptr;
 
   // ---- per-stage timing ----
   bool prof_on = false;
@@ -152,7 +160,7 @@ struct Ctx {
   bool gprof_on = false;
   hipEvent_t gev[2] = {nullptr, nullptr};
   int wall_khz = 0;
-  double gprof_ms[2] = {0.0, 0.0};
+  double gprof_ms[4] = {0.0, 0.0, 0.0, 0.0};   // internal (both phases), replay, phase 0, phase 1
   int64_t gprof_calls = 0;
 
   // ---- cost model ----

@@ -145,12 +145,43 @@ __device__ __forceinline__ float4 ntload(const float2* p) {
   return make_float4(v.x, v.y, v.z, v.w);
 }
 
+// Work list of one launch of a persistent internal kernel: static per-slot queues
+// (slot s takes tiles [start[s], start[s+1])) or, when ctr is set, one dynamic queue
+// tiles[first, first + count) in list order, each workgroup drawing its next tile
+// from the counter when it finishes the last one.  A launch on a counter draws
+// exactly count + gridDim.x tickets (every workgroup stops at its first ticket past
+// the list), so the counter needs no reset between launches: ticket t stands for
+// list position t mod (count + gridDim.x).  Launches on one counter must not overlap.
+struct TileQueue {
+  const int4* tiles;
+  const int32_t* start;        // static: slot ranges (absolute tile indices)
+  unsigned long long* ctr;     // dynamic: ticket counter (null: static)
+  int32_t first, count;
+};
+
+// Index of the workgroup's next tile, or -1 when it has none.  Every thread of the
+// workgroup calls it (the dynamic form has barriers); `it` starts at
+// q.start[blockIdx.x] and s_next is a workgroup-shared int.
+__device__ __forceinline__ int next_tile(const TileQueue& q, int& it, int* s_next) {
+  if (!q.ctr) return it < q.start[blockIdx.x + 1] ? it++ : -1;
+  if (threadIdx.x == 0) {
+    const unsigned long long T = (unsigned long long)(q.count) + gridDim.x;
+    const unsigned long long t = atomicAdd(q.ctr, 1ull) % T;
+    *s_next = t < (unsigned long long)(q.count) ? q.first + int(t) : -1;
+  }
+  __syncthreads();
+  const int ti = *s_next;
+  __syncthreads();
+  return ti;
+}
+
 template <bool F64, int RW>
 __global__ void __launch_bounds__(256) k_internal(const float2* __restrict__ hi, const float2* __restrict__ lo,
-                                                  const BlockDev* __restrict__ blocks, const int4* __restrict__ tiles,
-                                                  const int32_t* __restrict__ slot_start, const void* __restrict__ Hv,
-                                                  void* __restrict__ ev, void* __restrict__ jv, void* __restrict__ gv,
-                                                  unsigned long long* __restrict__ stamps) {
+                                                  const BlockDev* __restrict__ blocks, const TileQueue q,
+                                                  const void* __restrict__ Hv, void* __restrict__ ev,
+                                                  void* __restrict__ jv, void* __restrict__ gv,
+                                                  unsigned long long* __restrict__ stamps,
+                                                  unsigned long long* __restrict__ span) {
   using T = typename P<F64>::T;
   // RW rows per wave per sweep (4 in FP64, where hi + lo doubles the loads; 4 or 8 in mixed)
   const C2<T>* H = reinterpret_cast<const C2<T>*>(Hv);
@@ -159,8 +190,11 @@ __global__ void __launch_bounds__(256) k_internal(const float2* __restrict__ hi,
   C2<T>* go = reinterpret_cast<C2<T>*>(gv);
   const int slot = blockIdx.x;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  for (int ti = slot_start[slot]; ti < slot_start[slot + 1]; ++ti) {
-    const int4 tl = tiles[ti];        // block, row0, rows, slot
+  if (span && threadIdx.x == 0) span[2 * slot] = wall_clock64();
+  __shared__ int s_next;
+  int it = q.ctr ? 0 : q.start[slot];
+  for (int ti = next_tile(q, it, &s_next); ti >= 0; ti = next_tile(q, it, &s_next)) {
+    const int4 tl = q.tiles[ti];      // block, row0, rows, slot
     unsigned long long t_start = 0;
     if (stamps && threadIdx.x == 0) t_start = wall_clock64();
     const BlockDev B = blocks[tl.x];
@@ -241,6 +275,10 @@ __global__ void __launch_bounds__(256) k_internal(const float2* __restrict__ hi,
       }
     }
   }
+  if (span) {
+    __syncthreads();
+    if (threadIdx.x == 0) span[2 * slot + 1] = wall_clock64();
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -290,93 +328,132 @@ __global__ void k_split_h(const double2* X, int64_t nsys, int64_t ne, int R, int
   Hs[3 * plane + o] = __bf16(im - float(ih));
 }
 
-template <int NCG>
+// One wave computes RG 16-row groups x NCG 16-column groups: the H fragments of a K
+// chunk are loaded once for the RG row groups, the next chunk's A and H fragments are
+// loaded while the current chunk's MFMAs run, and the 12 products of a chunk are issued
+// term by term across all accumulators, so that dependent MFMAs are far apart.
+template <int NCG, int RG>
 __global__ void __launch_bounds__(256) k_internal_mfma(const float2* __restrict__ hi, const BlockDev* __restrict__ blocks,
-                                                       const int4* __restrict__ tiles,
-                                                       const int32_t* __restrict__ slot_start,
+                                                       const TileQueue q0, const TileQueue q1,
                                                        const int64_t* __restrict__ hoff, const __bf16* __restrict__ Hs,
                                                        int64_t plane, int64_t ldh,
                                                        const float2* __restrict__ H64, int64_t ne, int ncol,
                                                        float2* __restrict__ E, float2* __restrict__ J) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int lr = lane & 15, lg = lane >> 4;
-  for (int ti = slot_start[blockIdx.x]; ti < slot_start[blockIdx.x + 1]; ++ti) {
-    const int4 tl = tiles[ti];
+  __shared__ int s_next;
+  // the two phases' lists (rows of M_i, then rows of Z_i), one after the other
+  for (int phase = 0; phase < 2; ++phase) {
+   const TileQueue& q = phase == 0 ? q0 : q1;
+   int it = q.ctr ? 0 : q.start[blockIdx.x];
+   for (int ti = next_tile(q, it, &s_next); ti >= 0; ti = next_tile(q, it, &s_next)) {
+    const int4 tl = q.tiles[ti];
     const BlockDev B = blocks[tl.x];
     const int n = B.n, ld = (n + 1) & ~1, rend = tl.y + tl.z;
-    for (int r0 = tl.y + 16 * wave; r0 < rend; r0 += 64) {
-      f32x4 acc[NCG][4];
+    const int64_t h0 = hoff[tl.x];
+    for (int r0 = tl.y + 16 * RG * wave; r0 < rend; r0 += 64 * RG) {
+      f32x4 acc[RG][NCG][4];
 #pragma unroll
-      for (int g = 0; g < NCG; ++g)
+      for (int r = 0; r < RG; ++r)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) acc[g][q] = f32x4{0.f, 0.f, 0.f, 0.f};
-      const int row = r0 + lr;
-      const float2* arow = hi + B.off + int64_t(row) * ld;
-      // A fragment of the K chunk starting at k0: 8 complex (4 pairs), zero past the row
-      auto load_a = [&](int k0, float4* a) {
+        for (int g = 0; g < NCG; ++g)
 #pragma unroll
-        for (int p = 0; p < 4; ++p) {
-          const int kk = k0 + 8 * lg + 2 * p;
-          a[p] = (row < rend && kk < ld) ? ntload(arow + kk) : make_float4(0.f, 0.f, 0.f, 0.f);
+          for (int q = 0; q < 4; ++q) acc[r][g][q] = f32x4{0.f, 0.f, 0.f, 0.f};
+      // A fragments of the K chunk at k0: 8 complex (4 pairs) per row group, zero past the tile or row
+      auto load_a = [&](int k0, float4 (*a)[4]) {
+#pragma unroll
+        for (int r = 0; r < RG; ++r) {
+          const int row = r0 + 16 * r + lr;
+          const float2* arow = hi + B.off + int64_t(row) * ld;
+#pragma unroll
+          for (int p = 0; p < 4; ++p) {
+            const int kk = k0 + 8 * lg + 2 * p;
+            a[r][p] = (row < rend && kk < ld) ? ntload(arow + kk) : make_float4(0.f, 0.f, 0.f, 0.f);
+          }
         }
       };
-      float4 a_cur[4], a_nxt[4];
-      load_a(0, a_cur);
-      for (int k0 = 0; k0 < n; k0 += 32) {
-        if (k0 + 32 < n) load_a(k0 + 32, a_nxt);
-        float re[8], im[8];
-#pragma unroll
-        for (int p = 0; p < 4; ++p) {
-          re[2 * p] = a_cur[p].x; im[2 * p] = a_cur[p].y;
-          re[2 * p + 1] = a_cur[p].z; im[2 * p + 1] = a_cur[p].w;
-        }
-        bf16x8 arh, arl, aih, ail;
-        split_bf16(re, arh, arl);
-        split_bf16(im, aih, ail);
-        const int64_t kb = hoff[tl.x] + k0 + 8 * lg;
+      // H fragments of the K chunk at k0: four split planes per column group
+      auto load_h = [&](int k0, bf16x8 (*h)[4]) {
+        const int64_t kb = h0 + k0 + 8 * lg;
 #pragma unroll
         for (int g = 0; g < NCG; ++g) {
           const int64_t o = int64_t(16 * g + lr) * ldh + kb;
-          const bf16x8 hrh = *reinterpret_cast<const bf16x8*>(Hs + o);
-          const bf16x8 hrl = *reinterpret_cast<const bf16x8*>(Hs + plane + o);
-          const bf16x8 hih = *reinterpret_cast<const bf16x8*>(Hs + 2 * plane + o);
-          const bf16x8 hil = *reinterpret_cast<const bf16x8*>(Hs + 3 * plane + o);
-          acc[g][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(arh, hrh, acc[g][0], 0, 0, 0);
-          acc[g][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(arh, hrl, acc[g][0], 0, 0, 0);
-          acc[g][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(arl, hrh, acc[g][0], 0, 0, 0);
-          acc[g][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aih, hih, acc[g][1], 0, 0, 0);
-          acc[g][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aih, hil, acc[g][1], 0, 0, 0);
-          acc[g][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ail, hih, acc[g][1], 0, 0, 0);
-          acc[g][2] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(arh, hih, acc[g][2], 0, 0, 0);
-          acc[g][2] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(arh, hil, acc[g][2], 0, 0, 0);
-          acc[g][2] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(arl, hih, acc[g][2], 0, 0, 0);
-          acc[g][3] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aih, hrh, acc[g][3], 0, 0, 0);
-          acc[g][3] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aih, hrl, acc[g][3], 0, 0, 0);
-          acc[g][3] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ail, hrh, acc[g][3], 0, 0, 0);
-        }
 #pragma unroll
-        for (int p = 0; p < 4; ++p) a_cur[p] = a_nxt[p];
+          for (int pl = 0; pl < 4; ++pl) h[g][pl] = *reinterpret_cast<const bf16x8*>(Hs + pl * plane + o);
+        }
+      };
+      float4 a_cur[RG][4], a_nxt[RG][4];
+      bf16x8 h_cur[NCG][4], h_nxt[NCG][4];
+      load_a(0, a_cur);
+      load_h(0, h_cur);
+      for (int k0 = 0; k0 < n; k0 += 32) {
+        const bool more = k0 + 32 < n;
+        if (more) {
+          load_a(k0 + 32, a_nxt);
+          load_h(k0 + 32, h_nxt);
+        }
+        bf16x8 ah[RG][2], al[RG][2];   // [r][0]: real part, [r][1]: imaginary part
+#pragma unroll
+        for (int r = 0; r < RG; ++r) {
+          float re[8], im[8];
+#pragma unroll
+          for (int p = 0; p < 4; ++p) {
+            re[2 * p] = a_cur[r][p].x; im[2 * p] = a_cur[r][p].y;
+            re[2 * p + 1] = a_cur[r][p].z; im[2 * p + 1] = a_cur[r][p].w;
+          }
+          split_bf16(re, ah[r][0], al[r][0]);
+          split_bf16(im, ah[r][1], al[r][1]);
+        }
+        // accumulators: 0 = Ar Hr, 1 = Ai Hi, 2 = Ar Hi, 3 = Ai Hr; planes: 0 Hr hi, 1 Hr lo, 2 Hi hi, 3 Hi lo
+        // term 0: a_hi b_hi, term 1: a_hi b_lo, term 2: a_lo b_hi
+#pragma unroll
+        for (int term = 0; term < 3; ++term)
+#pragma unroll
+          for (int r = 0; r < RG; ++r)
+#pragma unroll
+            for (int g = 0; g < NCG; ++g)
+#pragma unroll
+              for (int q = 0; q < 4; ++q) {
+                const int ai = (q == 0 || q == 2) ? 0 : 1;     // Ar for accumulators 0, 2; Ai for 1, 3
+                const int bp = (q == 0 || q == 3) ? 0 : 2;     // Hr for accumulators 0, 3; Hi for 1, 2
+                const bf16x8 av = term == 2 ? al[r][ai] : ah[r][ai];
+                const bf16x8 bv = term == 1 ? h_cur[g][bp + 1] : h_cur[g][bp];
+                acc[r][g][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[r][g][q], 0, 0, 0);
+              }
+        if (more) {
+#pragma unroll
+          for (int r = 0; r < RG; ++r)
+#pragma unroll
+            for (int p = 0; p < 4; ++p) a_cur[r][p] = a_nxt[r][p];
+#pragma unroll
+          for (int g = 0; g < NCG; ++g)
+#pragma unroll
+            for (int pl = 0; pl < 4; ++pl) h_cur[g][pl] = h_nxt[g][pl];
+        }
       }
       // epilogue: e rows (row < n) and j = H - g rows (row >= n), column 16 g + lr
 #pragma unroll
-      for (int g = 0; g < NCG; ++g) {
-        const int col = 16 * g + lr;
-        if (col >= ncol) continue;
+      for (int r = 0; r < RG; ++r)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int rr = r0 + 4 * lg + q;
-          if (rr >= rend) continue;
-          const float yr = acc[g][0][q] - acc[g][1][q], yi = acc[g][2][q] + acc[g][3][q];
-          if (rr < n) {
-            E[int64_t(col) * ne + B.e0 + rr] = make_float2(yr, yi);
-          } else {
-            const int64_t k = int64_t(col) * ne + B.e0 + (rr - n);
-            const float2 h = H64[k];
-            J[k] = make_float2(h.x - yr, h.y - yi);
+        for (int g = 0; g < NCG; ++g) {
+          const int col = 16 * g + lr;
+          if (col >= ncol) continue;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int rr = r0 + 16 * r + 4 * lg + q;
+            if (rr >= rend) continue;
+            const float yr = acc[r][g][0][q] - acc[r][g][1][q], yi = acc[r][g][2][q] + acc[r][g][3][q];
+            if (rr < n) {
+              E[int64_t(col) * ne + B.e0 + rr] = make_float2(yr, yi);
+            } else {
+              const int64_t k = int64_t(col) * ne + B.e0 + (rr - n);
+              const float2 h = H64[k];
+              J[k] = make_float2(h.x - yr, h.y - yi);
+            }
           }
         }
-      }
     }
+   }
   }
 }
 
@@ -594,12 +671,33 @@ __global__ void k_copy_out(const void* in, double2* out, int64_t n) {
   out[i] = make_double2(double(v.x), double(v.y));
 }
 
+// Work list of a phase of the internal tiles (0: rows of M_i, 1: rows of Z_i) on
+// dynamic-dispatch counter `ctr` (used in the dynamic scheduling modes).
+TileQueue phase_queue(Ctx& c, int phase, int ctr) {
+  TileQueue q;
+  q.tiles = c.d_tiles.as<int4>();
+  q.start = c.d_slot_start.as<int32_t>() + size_t(phase) * (c.slots + 1);
+  q.ctr = c.dynamic ? c.d_qctr.as<unsigned long long>() + ctr : nullptr;
+  q.first = c.phase_first[phase];
+  q.count = c.phase_count[phase];
+  return q;
+}
+
+// One phase of the internal product: 0 = rows of M_i (g = M H, j = H - g), 1 = rows
+// of Z_i (e = Z H); phase -1 runs both, one after the other, on stream s.
 template <bool F64>
-void internal_launch(Ctx& c, const void* H, void* e, void* j, void* g, hipStream_t s) {
-  unsigned long long* st = c.record || c.gprof_on ? c.d_stamps.as<unsigned long long>() : nullptr;
+void internal_launch(Ctx& c, const void* H, void* e, void* j, void* g, hipStream_t s, int phase = -1) {
+  if (phase < 0) {
+    internal_launch<F64>(c, H, e, j, g, s, 0);
+    internal_launch<F64>(c, H, e, j, g, s, 1);
+    return;
+  }
+  unsigned long long* st = c.record ? c.d_stamps.as<unsigned long long>() : nullptr;
+  unsigned long long* sp = c.gprof_on ? c.d_span.as<unsigned long long>() + 2 * size_t(c.slots) * phase : nullptr;
+  const TileQueue q = phase_queue(c, phase, phase);
   auto go = [&](auto kern) {
     hipLaunchKernelGGL(kern, dim3(unsigned(c.slots)), dim3(256), 0, s, c.d_hi.as<float2>(), c.d_lo.as<float2>(),
-                       c.d_blocks.as<BlockDev>(), c.d_tiles.as<int4>(), c.d_slot_start.as<int32_t>(), H, e, j, g, st);
+                       c.d_blocks.as<BlockDev>(), q, H, e, j, g, st, sp);
   };
   if (F64) go(k_internal<true, 4>);
   else if (c.rw_mixed == 4) go(k_internal<false, 4>);
@@ -656,9 +754,19 @@ void matvec_t(Ctx& c, const void* x, void* y, void* e_out, void* g_out, void* a_
   // A1 + A2
   void* ev = ext_e ? ext_e : c.d_e.p;
   void* jv = ext_j ? ext_j : c.d_j.p;
+  // The rows of Z_i (e, needed only by the RWG rows at the end) run on a third
+  // stream, concurrently with the projection and the convolution of j, once the
+  // rows of M_i (g, j) are done.
+  const bool overlap_z = overlap && c.s_int && !ext_e;
   if (!ext_e) {
     mark(0);
-    internal_launch<F64>(c, X, ev, jv, g_out ? c.d_g.p : nullptr, s);
+    internal_launch<F64>(c, X, ev, jv, g_out ? c.d_g.p : nullptr, s, overlap_z ? 0 : -1);
+    if (overlap_z) {
+      SLIM_HIP(hipEventRecord(c.ev_zfork, s));
+      SLIM_HIP(hipStreamWaitEvent(c.s_int, c.ev_zfork, 0));
+      internal_launch<F64>(c, X, ev, jv, nullptr, c.s_int, 1);
+      SLIM_HIP(hipEventRecord(c.ev_zjoin, c.s_int));
+    }
     mark(0);
   }
   if (c.plain) {
@@ -693,6 +801,7 @@ void matvec_t(Ctx& c, const void* x, void* y, void* e_out, void* g_out, void* a_
       SLIM_HIP(hipGetLastError());
     }
     mark(3);
+    if (overlap_z) SLIM_HIP(hipStreamWaitEvent(s, c.ev_zjoin, 0));
     mark(4);
     hipLaunchKernelGGL((k_rows_A<F64, true>), dim3(nblk(ne, 4)), dim3(256), 0, s, c.d_we_base.as<int32_t>(),
                        F64 ? c.d_we_w64.p : c.d_we_w32.p, c.d_oct_out.p, N3, Nx, NxNy, c.d_nA_ptr.as<int64_t>(),
@@ -802,27 +911,34 @@ void matvec_graph(Ctx& c, slim_prec prec, const void* x, void* y, hipStream_t s)
     return;
   }
   // graph-path timing: the replay between two events on the caller's stream; the
-  // internal kernel from its own per-tile wall-clock stamps (first start to last end
-  // over all workgroups), which the captured launch writes; synchronous
+  // internal kernel from its own wall-clock stamps (first workgroup start to last
+  // workgroup end), which the captured launch writes; synchronous
   SLIM_HIP(hipEventRecord(c.gev[0], s));
   SLIM_HIP(hipGraphLaunch(exec, s));
   SLIM_HIP(hipEventRecord(c.gev[1], s));
   SLIM_HIP(hipEventSynchronize(c.gev[1]));
   float t_all = 0.f;
   SLIM_HIP(hipEventElapsedTime(&t_all, c.gev[0], c.gev[1]));
-  std::vector<unsigned long long> st(2 * c.tiles.size());
-  SLIM_HIP(hipMemcpy(st.data(), c.d_stamps.p, st.size() * 8, hipMemcpyDeviceToHost));
-  unsigned long long t0 = ~0ull, t1 = 0;
-  for (size_t k = 0; k < c.tiles.size(); ++k) {
-    t0 = std::min(t0, st[2 * k]);
-    t1 = std::max(t1, st[2 * k + 1]);
-  }
+  std::vector<unsigned long long> st(4 * size_t(c.slots));
+  SLIM_HIP(hipMemcpy(st.data(), c.d_span.p, st.size() * 8, hipMemcpyDeviceToHost));
   if (c.wall_khz <= 0) {
     int khz = 0;
     SLIM_HIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, c.device));
     c.wall_khz = khz;
   }
-  c.gprof_ms[0] += t1 > t0 && c.wall_khz > 0 ? double(t1 - t0) / double(c.wall_khz) : 0.0;
+  // per phase: first workgroup start to last workgroup end
+  unsigned long long a0 = ~0ull, a1 = 0;
+  for (int ph = 0; ph < 2; ++ph) {
+    unsigned long long t0 = ~0ull, t1 = 0;
+    for (int k = 0; k < c.slots; ++k) {
+      t0 = std::min(t0, st[2 * (size_t(ph) * c.slots + k)]);
+      t1 = std::max(t1, st[2 * (size_t(ph) * c.slots + k) + 1]);
+    }
+    c.gprof_ms[2 + ph] += t1 > t0 && c.wall_khz > 0 ? double(t1 - t0) / double(c.wall_khz) : 0.0;
+    a0 = std::min(a0, t0);
+    a1 = std::max(a1, t1);
+  }
+  c.gprof_ms[0] += a1 > a0 && c.wall_khz > 0 ? double(a1 - a0) / double(c.wall_khz) : 0.0;
   c.gprof_ms[1] += t_all;
   c.gprof_calls++;
 }
@@ -925,14 +1041,14 @@ void matvec_block(Ctx& c, slim_prec prec, const void* X, void* Y, int R, hipStre
     const int ncol = std::min(64, R - col0), ncg = (ncol + 15) / 16;
     auto go = [&](auto kern) {
       hipLaunchKernelGGL(kern, dim3(unsigned(c.slots)), dim3(256), 0, s, c.d_hi.as<float2>(), c.d_blocks.as<BlockDev>(),
-                         c.d_tiles.as<int4>(), c.d_slot_start.as<int32_t>(), c.d_blk_hoff.as<int64_t>(),
+                         phase_queue(c, 0, 2), phase_queue(c, 1, 3), c.d_blk_hoff.as<int64_t>(),
                          Hs + int64_t(col0) * c.blk_ldh, plane, c.blk_ldh, c.d_blk_h64.as<float2>() + int64_t(col0) * ne,
                          ne, ncol, c.d_blk_e.as<float2>() + int64_t(col0) * ne, c.d_blk_j.as<float2>() + int64_t(col0) * ne);
     };
-    if (ncg == 1) go(k_internal_mfma<1>);
-    else if (ncg == 2) go(k_internal_mfma<2>);
-    else if (ncg == 3) go(k_internal_mfma<3>);
-    else go(k_internal_mfma<4>);
+    if (ncg == 1) go(k_internal_mfma<1, 2>);
+    else if (ncg == 2) go(k_internal_mfma<2, 2>);
+    else if (ncg == 3) go(k_internal_mfma<3, 1>);
+    else go(k_internal_mfma<4, 1>);
     SLIM_HIP(hipGetLastError());
   }
   if (c.prof_on) c.prof_mark(0, s);

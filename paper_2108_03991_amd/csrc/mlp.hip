@@ -8,7 +8,14 @@
 // the block of object i with n_i unknowns):
 //   log n_i, log(aspect of the object's bounding box), log(skin depth / size)
 //   (size = square root of the surface area), log rows, (n_i mod 64)/64,
-// standardised; target: log(tile time).  Loss: mean squared error.
+//   log of the row sweeps of the busiest wave (rows over four waves of `rows per
+//   wave` rows, rounded up) and log of the 256-column chunks of a row (row length
+//   rounded up): the persistent kernel's loop counts for the tile,
+// standardised.  Target: log(tile time / (sweeps x chunks)), the time per inner
+// iteration, so that the network learns a bounded correction to the loop count
+// and a tile larger than any it was trained on still scales with its loop count;
+// the predicted tile time is exp(output) x sweeps x chunks.  Loss: mean squared
+// error.
 #include <algorithm>
 #include <mutex>
 
@@ -184,9 +191,11 @@ namespace {
 
 }  // namespace
 
-constexpr int kFeat = 5;
+constexpr int kFeat = 7;
+static_assert(kFeat <= FMAX, "feature count within the network's input bound");
 
-void tile_features(const Ctx& c, int block, int rows, float* f) {
+// Raw (unstandardised) features of a tile: panel of `rows` rows of block `block`.
+void tile_features_raw(const Ctx& c, int block, int rows, float* f) {
   // object geometry from its triangles
   const RWGTable& r = c.rwg;
   const Mesh& m = c.mesh;
@@ -204,13 +213,25 @@ void tile_features(const Ctx& c, int block, int rows, float* f) {
   std::sort(d, d + 3);
   const Material& mt = c.mats.empty() ? Material{} : c.mats[block];
   const double delta = 1.0 / std::sqrt(kPi * c.freq * kMu0 * mt.mu_r * std::max(mt.sigma, 1e-300));
-  const int n = c.blocks[block].n;
-  float raw[kFeat] = {float(std::log(double(n))), float(std::log(d[2] / std::max(d[0], 1e-30))),
-                      float(std::log(delta / std::sqrt(S))), float(std::log(double(rows))), float((n % 64) / 64.0)};
-  for (int k = 0; k < kFeat; ++k) {
-    const float mu = c.mlp_mu.empty() ? 0.f : c.mlp_mu[k];
-    const float sd = c.mlp_sd.empty() ? 1.f : c.mlp_sd[k];
-    f[k] = (raw[k] - mu) / sd;
+  const int n = c.blocks[block].n, ld = (n + 1) & ~1;
+  const int sweeps = (rows + 4 * c.rw_mixed - 1) / (4 * c.rw_mixed), chunks = (ld + 255) / 256;
+  const float raw[kFeat] = {float(std::log(double(n))), float(std::log(d[2] / std::max(d[0], 1e-30))),
+                            float(std::log(delta / std::sqrt(S))), float(std::log(double(rows))),
+                            float((n % 64) / 64.0), float(std::log(double(sweeps))),
+                            float(std::log(double(chunks)))};
+  for (int k = 0; k < kFeat; ++k) f[k] = raw[k];
+}
+
+// Raw features and log tile time (wall-clock ticks) of the last recorded tiles.
+void recorded_samples(const Ctx& c, std::vector<float>& X, std::vector<float>& T) {
+  const int64_t nt = int64_t(c.tiles.size());
+  SLIM_REQUIRE(int64_t(c.last_stamps.size()) == 2 * nt && nt > 0, SLIM_E_STATE, "no recorded tile timings");
+  X.assign(size_t(nt) * kFeat, 0.f);
+  T.assign(nt, 0.f);
+  for (int64_t k = 0; k < nt; ++k) {
+    tile_features_raw(c, c.tiles[k].block, c.tiles[k].rows, &X[size_t(k) * kFeat]);
+    const double dt = std::max(1.0, c.last_stamps[2 * k + 1] - c.last_stamps[2 * k]);
+    T[k] = float(std::log(dt));
   }
 }
 
@@ -238,20 +259,30 @@ float mlp_predict_host(const Ctx& c, const float* x) {
   return out;
 }
 
-// Train on the last recorded tiles (slim_sched_record + slim_internal_apply with timing).
-double mlp_train(Ctx& c, int epochs, double lr) {
-  const int64_t nt = int64_t(c.tiles.size());
-  SLIM_REQUIRE(int64_t(c.last_stamps.size()) == 2 * nt && nt > 0, SLIM_E_STATE, "no recorded tile timings");
-  const int F = kFeat;
-  // features (raw), then standardise
-  c.mlp_mu.clear();
-  c.mlp_sd.clear();
-  std::vector<float> X(size_t(nt) * F), T(nt);
-  for (int64_t k = 0; k < nt; ++k) {
-    tile_features(c, c.tiles[k].block, c.tiles[k].rows, &X[size_t(k) * F]);
-    const double dt = std::max(1.0, c.last_stamps[2 * k + 1] - c.last_stamps[2 * k]);
-    T[k] = float(std::log(dt));
+// Predicted time of a tile (wall-clock ticks): the network's time per inner iteration
+// times the tile's loop count (row sweeps x column chunks).
+double mlp_predict_time(const Ctx& c, int block, int rows) {
+  float f[FMAX];
+  tile_features_raw(c, block, rows, f);
+  const double loops = std::exp(double(f[5]) + double(f[6]));
+  for (int k = 0; k < kFeat; ++k) {
+    const float mu = c.mlp_mu.empty() ? 0.f : c.mlp_mu[k];
+    const float sd = c.mlp_sd.empty() ? 1.f : c.mlp_sd[k];
+    f[k] = (f[k] - mu) / sd;
   }
+  return std::exp(double(mlp_predict_host(c, f))) * loops;
+}
+
+// Train the context's cost model on samples (raw features X, nt x kFeat; log tile
+// times T): standardise the features, initialise deterministically, run Adam.
+double mlp_train_on(Ctx& c, std::vector<float> X, const std::vector<float>& T, int epochs, double lr) {
+  const int64_t nt = int64_t(T.size());
+  SLIM_REQUIRE(nt > 0 && int64_t(X.size()) == nt * kFeat, SLIM_E_ARG, "no training samples");
+  SLIM_REQUIRE(nt <= (int64_t(1) << 31) - 64, SLIM_E_ARG, "too many training samples");
+  const int F = kFeat;
+  // target: log time per inner iteration (raw features 5 and 6: log sweeps, log chunks)
+  std::vector<float> Tr(T);
+  for (int64_t k = 0; k < nt; ++k) Tr[k] -= X[size_t(k) * F + 5] + X[size_t(k) * F + 6];
   std::vector<float> mu(F, 0.f), sd(F, 0.f);
   for (int64_t k = 0; k < nt; ++k)
     for (int f = 0; f < F; ++f) mu[f] += X[size_t(k) * F + f] / float(nt);
@@ -272,7 +303,7 @@ double mlp_train(Ctx& c, int epochs, double lr) {
   for (int i = 0; i < HID * HID; ++i) p[HID * F + HID + i] = urand() * std::sqrt(3.f / HID);
   for (int i = 0; i < HID; ++i) p[HID * F + HID + HID * HID + HID + i] = urand() * std::sqrt(3.f / HID);
   float tmean = 0.f;
-  for (float v : T) tmean += v / float(nt);
+  for (float v : Tr) tmean += v / float(nt);
   p[np - 1] = tmean;
   DevBuf dp, dg, dm, dv, dX, dT, dy, dl, part, pl;
   dp.upload(p);
@@ -282,7 +313,7 @@ double mlp_train(Ctx& c, int epochs, double lr) {
   SLIM_HIP(hipMemset(dm.p, 0, dm.bytes));
   SLIM_HIP(hipMemset(dv.p, 0, dv.bytes));
   dX.upload(X);
-  dT.upload(T);
+  dT.upload(Tr);
   dy.alloc(size_t(nt) * 4);
   dl.alloc(4);
   hipStream_t s = nullptr;
@@ -305,6 +336,13 @@ double mlp_train(Ctx& c, int epochs, double lr) {
   c.mlp_mu = mu;
   c.mlp_sd = sd;
   return double(loss);
+}
+
+// Train on the last recorded tiles (slim_sched_record + slim_internal_apply with timing).
+double mlp_train(Ctx& c, int epochs, double lr) {
+  std::vector<float> X, T;
+  recorded_samples(c, X, T);
+  return mlp_train_on(c, X, T, epochs, lr);
 }
 
 }  // namespace slim
@@ -341,6 +379,55 @@ slim_status slim_mlp_forward_backward_noalloc(int32_t F, int32_t B, const float*
   } catch (const Error& e) {
     return e.code;
   } catch (...) {
+    return SLIM_E_HIP;
+  }
+}
+
+slim_status slim_sched_export(slim_ctx* h, double* out, int64_t* n) {
+  if (!h || !n) return SLIM_E_ARG;
+  try {
+    h->c.last_error.clear();
+    std::vector<float> X, T;
+    recorded_samples(h->c, X, T);
+    const int64_t cap = *n, nt = int64_t(T.size());
+    *n = nt;
+    if (!out) return SLIM_OK;
+    SLIM_REQUIRE(cap >= nt, SLIM_E_ARG, "sample buffer too small");
+    for (int64_t k = 0; k < nt; ++k) {
+      for (int f = 0; f < kFeat; ++f) out[(kFeat + 1) * k + f] = X[size_t(k) * kFeat + f];
+      out[(kFeat + 1) * k + kFeat] = T[k];
+    }
+    return SLIM_OK;
+  } catch (const Error& e) {
+    h->c.last_error = e.what();
+    return e.code;
+  } catch (const std::exception& e) {
+    h->c.last_error = e.what();
+    return SLIM_E_HIP;
+  }
+}
+
+slim_status slim_sched_train_data(slim_ctx* h, int64_t n, const double* data, int32_t epochs, double lr,
+                                  double* final_loss) {
+  if (!h || !data || n < 1) return SLIM_E_ARG;
+  try {
+    h->c.last_error.clear();
+    SLIM_REQUIRE(h->c.built, SLIM_E_STATE, "operator not built");
+    std::vector<float> X(size_t(n) * kFeat), T(n);
+    for (int64_t k = 0; k < n; ++k) {
+      for (int f = 0; f < kFeat; ++f) X[size_t(k) * kFeat + f] = float(data[(kFeat + 1) * k + f]);
+      T[k] = float(data[(kFeat + 1) * k + kFeat]);
+      for (int f = 0; f <= kFeat; ++f)
+        SLIM_REQUIRE(std::isfinite(data[(kFeat + 1) * k + f]), SLIM_E_ARG, "non-finite training sample");
+    }
+    double l = mlp_train_on(h->c, X, T, epochs > 0 ? epochs : 2000, lr > 0 ? lr : 3e-3);
+    if (final_loss) *final_loss = l;
+    return SLIM_OK;
+  } catch (const Error& e) {
+    h->c.last_error = e.what();
+    return e.code;
+  } catch (const std::exception& e) {
+    h->c.last_error = e.what();
     return SLIM_E_HIP;
   }
 }

@@ -140,6 +140,8 @@ def lib():
         L.slim_profile.argtypes = [vp, i32]
         L.slim_profile_read.argtypes = [vp, dp, C.POINTER(i64)]
         L.slim_matvec_block.argtypes = [vp, i32, vp, vp, i32, vp]
+        L.slim_sched_export.argtypes = [vp, dp, C.POINTER(i64)]
+        L.slim_sched_train_data.argtypes = [vp, i64, dp, i32, C.c_double, dp]
         L.slim_rhs_ports.argtypes = [vp, C.POINTER(Port), i32, vp, vp]
         L.slim_port_currents.argtypes = [vp, C.POINTER(Port), i32, vp, i32, dp, vp]
         for name in ("slim_create", "slim_set_mesh", "slim_set_materials", "slim_build", "slim_get_layout",
@@ -150,7 +152,7 @@ def lib():
                      "slim_precond_apply", "slim_get_precond", "slim_precond_partition", "slim_set_medium",
                      "slim_aim_convolve_layered", "slim_get_layered_kernels", "slim_layered_gammas",
                      "slim_matvec_block", "slim_rhs_ports", "slim_port_currents",
-                     "slim_mlp_forward_backward_noalloc"):
+                     "slim_mlp_forward_backward_noalloc", "slim_sched_export", "slim_sched_train_data"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -163,7 +165,8 @@ EXPORTS = ["slim_default_build_opts", "slim_create", "slim_destroy", "slim_last_
            "slim_profile", "slim_profile_read", "slim_aim_convolve", "slim_get_aim", "slim_get_near",
            "slim_precond_apply", "slim_get_precond", "slim_precond_partition", "slim_set_medium",
            "slim_aim_convolve_layered", "slim_get_layered_kernels", "slim_layered_gammas", "slim_matvec_block",
-           "slim_rhs_ports", "slim_port_currents", "slim_mlp_forward_backward_noalloc"]
+           "slim_rhs_ports", "slim_port_currents", "slim_mlp_forward_backward_noalloc", "slim_sched_export",
+           "slim_sched_train_data"]
 
 
 def _ptr(t):
@@ -394,6 +397,22 @@ class Context:
     def sched_train(self, epochs=2000, lr=3e-3):
         loss = C.c_double(0.0)
         self._check(lib().slim_sched_train(self._h, int(epochs), float(lr), C.byref(loss)))
+        return loss.value
+
+    def sched_export(self):
+        """Samples of the last recorded tiles: (n, 8) = seven raw features and log duration."""
+        n = C.c_int64(0)
+        self._check(lib().slim_sched_export(self._h, None, C.byref(n)))
+        out = np.zeros(8 * n.value)
+        self._check(lib().slim_sched_export(self._h, out.ctypes.data_as(C.POINTER(C.c_double)), C.byref(n)))
+        return out.reshape(-1, 8)
+
+    def sched_train_data(self, samples, epochs=2000, lr=3e-3):
+        """Train the cost model on samples in the sched_export layout; returns the final loss."""
+        a = np.ascontiguousarray(samples, dtype=np.float64)
+        loss = C.c_double(0.0)
+        self._check(lib().slim_sched_train_data(self._h, a.shape[0], a.ctypes.data_as(C.POINTER(C.c_double)),
+                                                int(epochs), float(lr), C.byref(loss)))
         return loss.value
 
     def sched_set_mode(self, mode):
