@@ -496,7 +496,10 @@ def main():
                     help="skip the GMRES time-to-1e-6 runs (mixed GMRES-IR vs FP64, plane-wave excitation)")
     ap.add_argument("--solve-max-iter", type=int, default=1000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--sched", type=int, default=0)
+    ap.add_argument("--sched", type=int, default=4,
+                    help="scheduling mode of the timed products: 0 LPT on flop counts, 1 LPT on the trained cost "
+                         "model, 2 naive, 3 dynamic dispatch in flop-count order, 4 dynamic dispatch in the trained "
+                         "model's order (the learned modes need the schedule study, which trains the model)")
     ap.add_argument("--copy-probe", type=float, default=0.0,
                     help="only run a plain device copy of this many GiB (HBM counter calibration) and exit")
     ap.add_argument("--no-sched-study", action="store_true",
@@ -536,7 +539,7 @@ def main():
     ctx.set_mesh(mesh.verts, mesh.tris, mesh.obj, mesh.n_obj)
     t0 = time.time()
     # the conductor-block preconditioner is only built for the solve
-    lay = ctx.build(freq=freq, grid=grid, sched_mode=args.sched, verbose=1, precond=0 if args.no_solve else 1)
+    lay = ctx.build(freq=freq, grid=grid, sched_mode=0, verbose=1, precond=0 if args.no_solve else 1)
     log("build: %.1f s, n_e %d n_t %d nnzA %d nnzP %d tiles %d slots %d" % (
         time.time() - t0, lay.n_e, lay.n_t, lay.nnz_near_A, lay.nnz_near_phi, lay.n_tiles, lay.slots))
     n = lay.n_sys
@@ -544,6 +547,18 @@ def main():
     y = torch.zeros_like(x)
     y64 = torch.zeros_like(x)
     stream = torch.cuda.current_stream()
+    # the schedule study records the tiles, trains the cost model on the GPU and measures
+    # the makespans of every packing; it leaves the context in the mode of the timed products
+    schedule = None
+    if not args.no_sched_study:
+        schedule = sched_study(ctx, lay, x, mode_after=args.sched)
+        log("schedule study: %s" % schedule)
+    elif args.sched in (1, 4):
+        log("no schedule study: the untrained cost model falls back to flop counts")
+        args.sched = 0 if args.sched == 1 else 3
+        ctx.sched_set_mode(args.sched)
+    elif args.sched != 0:
+        ctx.sched_set_mode(args.sched)
 
     def timed(prec, steps):
         ctx.profile(True)
@@ -626,6 +641,7 @@ def main():
             "n_e": lay.n_e, "n_t": lay.n_t, "n_obj": lay.n_obj, "nnz_near_A": lay.nnz_near_A,
             "nnz_near_phi": lay.nnz_near_phi, "internal_entries": lay.internal_entries,
             "tiles": lay.n_tiles, "slots": lay.slots, "build_s": lay.build_seconds,
+            "sched_mode": args.sched,
         },
         "fp64": {"value": args.steps / dt_fp64, "unit": "matvecs/s", "ms_per_step": 1e3 * dt_fp64 / args.steps,
                  "median_ms_per_step": step_ms["fp64"], "stage_ms": st_fp64,
@@ -645,9 +661,8 @@ def main():
                      "mean_launch_ms": 1e3 * t_int,
                      "staged_eager": {"achieved": achieved_eager / 1e9, "frac": achieved_eager / HBM_PEAK}},
     }
-    if not args.no_sched_study:
-        result["schedule"] = sched_study(ctx, lay, x, mode_after=args.sched)
-        log("schedule study: %s" % result["schedule"])
+    if schedule is not None:
+        result["schedule"] = schedule
     if not args.no_solve:
         result["solve"] = solve_study(ctx, lay, args.solve_max_iter)
         # the second half of the metric: seconds to a 1e-6 FP64 relative residual (null if not reached)

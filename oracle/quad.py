@@ -130,29 +130,39 @@ def polar_points(ro, V, levels, q, n_r, n_t):
 
 
 def _integrals_direct(ra, wa, rb, wb, Pa, Pb, k, want_k):
-    """The three pair integrals summed term by term from explicit point sets.
+    """The three pair integrals as iterated sums over explicit point sets: at every
+    test point r of the outer rule, the inner rule over the source triangle, then the
+    outer sum.  With f_m ~ (r - p_i) and f_n ~ (r' - q_j):
+      IS   = sum_o w_o sum_n w'_n G
+      IA_ij = sum_o w_o (r_o - p_i) . [sum_n w'_n G (r'_n - q_j)]
+      IK_ij = sum_o w_o (r_o - p_i) . [sum_n w'_n g (d x (r'_n - q_j))],  d = r - r',
+    g = dG/dR / R (grad_r G = g d); the inner brackets are formed from the sums
+    sum w' G, sum w' G r' and sum w' g d x r', sum w' g d at each test point.
 
     ra (B,No,3), wa (B,No); rb (B,No,Ni,3), wb (B,No,Ni); Pa, Pb (B,3,3) local vertices.
     """
     d = ra[:, :, None, :] - rb
     R = np.sqrt(np.sum(d * d, axis=-1))
     ekr = np.exp(-1j * k * R)
-    G = ekr / (4.0 * np.pi * R)
-    W = wa[:, :, None] * wb
-    A = ra[:, :, None, :] - Pa[:, None, :, :]           # (B,No,3i,3)
-    C = rb[:, :, :, None, :] - Pb[:, None, None, :, :]  # (B,No,Ni,3j,3)
-    IS = np.einsum('bon,bon->b', W, G)
-    IA = np.einsum('bon,boix,bonjx->bij', W * G, A, C, optimize=True)
+    WG = wb * (ekr / (4.0 * np.pi * R))                          # (B,No,Ni)
+    T0 = WG.sum(axis=2)                                          # inner sum of G
+    T1 = np.einsum('bon,bonx->box', WG, rb)                      # inner sum of G r'
+    inner = T1[:, :, None, :] - Pb[:, None, :, :] * T0[:, :, None, None]   # (B,No,3j,3)
+    A = ra[:, :, None, :] - Pa[:, None, :, :]                    # (B,No,3i,3)
+    IS = np.einsum('bo,bo->b', wa, T0)
+    IA = np.einsum('bo,boix,bojx->bij', wa, A, inner)
     IK = None
     if want_k:
-        g = -(1.0 + 1j * k * R) * ekr / (4.0 * np.pi * R ** 3)
-        X = np.cross(d[:, :, :, None, :], C)                  # d x (r' - q_j)
-        IK = np.einsum('bon,boix,bonjx->bij', W * g, A, X, optimize=True)
+        Wg = wb * (-(1.0 + 1j * k * R) * ekr / (4.0 * np.pi * R ** 3))
+        V1 = np.einsum('bon,bonx->box', Wg, np.cross(d, rb))      # inner sum of g d x r'
+        V2 = np.einsum('bon,bonx->box', Wg, d)                   # inner sum of g d
+        innerK = V1[:, :, None, :] - np.cross(V2[:, :, None, :], Pb[:, None, :, :])
+        IK = np.einsum('bo,boix,bojx->bij', wa, A, innerK)
     return IA, IS, IK
 
 
 def _integrals(ra, wa, rb, wb, Pa, Pb, k, want_k):
-    """Same sums as _integrals_direct, through moments in coordinates centred on Ta.
+    """The same sums as _integrals_direct, through moments in coordinates centred on Ta.
 
     With a = r - c, b = r' - c, P_i = p_i - c, Q_j = q_j - c (c = centroid of Ta):
       (a - P_i).(b - Q_j) = a.b - P_i.b - Q_j.a + P_i.Q_j
@@ -197,9 +207,10 @@ DEFAULT_DIRECT = True
 def pair_integrals(Va, Vb, k, near, coplanar, qp: QuadParams, want_k=True, batch=64, direct=None):
     """IA (B,3,3), IS (B,), IK (B,3,3) for triangle pairs (Va[b], Vb[b]).
 
-    The sums are taken term by term (_integrals_direct) unless direct=False asks for
-    the centroid-moment form (_integrals), a faster rearrangement of the same sums
-    that the tests pin against the direct one on both rules.
+    The sums are taken as iterated integrals (_integrals_direct: inner rule at every
+    test point, then the outer rule) unless direct=False asks for the centroid-moment
+    form (_integrals), a rearrangement of the same sums that the tests pin against the
+    iterated one on both rules.
     """
     if direct is None:
         direct = DEFAULT_DIRECT

@@ -268,11 +268,13 @@ __global__ void k_to_c64(const double* in, float* out, int64_t n2) {
 }
 
 // octant [0, Nz] x [0, Ny] x [0, Nx] of the (2N)^3 spectrum, complex128 and complex64
+// The octant k in [0, N] of the full spectrum, stored in the order [ky][kz][kx] (a
+// batch of adjacent kx lines of the fused z pass reads one contiguous stretch).
 __global__ void k_spectrum_octant(const double2* full, int Nx, int Ny, int Nz, double2* o128, float2* o64) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  const int64_t X1 = Nx + 1, Y1 = Ny + 1;
-  if (i >= X1 * Y1 * (Nz + 1)) return;
-  const int64_t x = i % X1, y = (i / X1) % Y1, z = i / (X1 * Y1);
+  const int64_t X1 = Nx + 1, Y1 = Ny + 1, Z1 = Nz + 1;
+  if (i >= X1 * Y1 * Z1) return;
+  const int64_t x = i % X1, z = (i / X1) % Z1, y = i / (X1 * Z1);
   const double2 v = full[(z * (2 * Ny) + y) * (2 * Nx) + x];
   o128[i] = v;
   o64[i] = make_float2(float(v.x), float(v.y));

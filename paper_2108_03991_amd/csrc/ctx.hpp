@@ -96,8 +96,7 @@ struct Ctx {
   // interpolation W = P^T (basis-major: base node + 27 weights per component)
   DevBuf d_we_base, d_we_w32, d_we_w64, d_wt_base, d_wt_w32, d_wt_w64;
   // Green's function spectrum on the (2N)^3 grid, scaled by 1/(2N)^3
-  DevBuf d_ghat64, d_ghat128;           // octant [kz][ky][kx]
-  DevBuf d_ghatz64, d_ghatz128;         // the same octant in the fused z pass's order [ky][kz][kx]
+  DevBuf d_ghat64, d_ghat128;           // octant k in [0, N], order [ky][kz][kx]
   DevBuf d_tw64, d_tw128;               // twiddles for each axis length
   // FFT work arrays (4 components)
   DevBuf d_oct_in, d_oct_in32;          // projected sources: complex128 / complex64 (zero off the occupied nodes)

@@ -151,7 +151,7 @@ template <class T> __device__ __forceinline__ void st_stream(C2<T>* p, C2<T> v) 
   __builtin_nontemporal_store(v.y, &p->y);
 }
 
-// MODE 0: forward, 1: inverse, 2: forward, multiply, inverse.
+// MODE 0: forward, 1: inverse.
 // CONTIG: lines are contiguous (in_e == 1), batch = consecutive lines along o1;
 // otherwise the batch is W = ELEMS/L adjacent lines (o1 stride 1) for coalescing.
 // Batch size in elements: strided passes keep 16 adjacent complex64 lines (128-byte
@@ -207,28 +207,6 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_pass(PassArgs a) {
   __syncthreads();
   if (MODE == 1) fft_batch<T, L, ELEMS, true>(lds, tw);
   else fft_batch<T, L, ELEMS, false>(lds, tw);
-  if (MODE == 2) {
-    const C2<T>* G = reinterpret_cast<const C2<T>*>(a.mul);
-    C2<T> gv[PER];
-#pragma unroll
-    for (int p = 0; p < PER; ++p) {
-      int b, i;
-      coords(p, b, i);
-      const int o1 = g1 + b;
-      const int m1 = o1 <= a.h_o1 ? o1 : 2 * a.h_o1 - o1, m2 = o2 <= a.h_o2 ? o2 : 2 * a.h_o2 - o2,
-                me = i <= a.h_e ? i : 2 * a.h_e - i;
-      gv[p] = {T(0), T(0)};
-      if (o1 < a.n1) gv[p] = G[m1 * a.mul_o1 + m2 * a.mul_o2 + int64_t(me) * a.mul_e];
-    }
-#pragma unroll
-    for (int p = 0; p < PER; ++p) {
-      int b, i;
-      coords(p, b, i);
-      if (g1 + b < a.n1) lds[pidx<L>(b, i)] = cmul(lds[pidx<L>(b, i)], gv[p]);
-    }
-    __syncthreads();
-    fft_batch<T, L, ELEMS, true>(lds, tw);
-  }
 #pragma unroll
   for (int p = 0; p < PER; ++p) {
     int b, i;
@@ -237,6 +215,107 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_pass(PassArgs a) {
     if (o1 < a.n1 && i < a.n_out)
       st_stream(out + (o1 * a.out_o1 + out_o2 + boff(i, a.out_e, a.out_e_hi, a.out_e_sh)), lds[pidx<L>(b, i)]);
   }
+}
+
+// Fused z step of the free-space convolution: per batch of W adjacent (kx, ky) lines,
+// forward FFT along z, product with the spectrum G^, inverse FFT, lower half kept.
+// G^ is even in kz, so a batch reads its L/2 + 1 distinct values (z-pass layout
+// [ky][kz][kx]: one contiguous stretch per batch) and applies each to kz and L - kz.
+// The component is the fastest grid index, so the workgroups of one batch run
+// together and share its G^ values through L2.  Strided lines as in k_fft_pass
+// (b = line in the batch, fastest).
+template <class T, int L>
+__global__ void __launch_bounds__(kFftThreads) k_fft_zconv(PassArgs a, int ncomp) {
+  constexpr int ELEMS = batch_elems<T, false>();
+  constexpr int W = ELEMS / L;
+  constexpr int PER = ELEMS / kFftThreads;
+  constexpr int NPAIR = W * (L / 2 + 1);
+  constexpr int PG = (NPAIR + kFftThreads - 1) / kFftThreads;
+  extern __shared__ unsigned char smem_raw[];
+  C2<T>* lds = reinterpret_cast<C2<T>*>(smem_raw);
+  constexpr bool TW_LDS = sizeof(T) == 4;
+  C2<T>* tw_lds = lds + W * line_stride<L>();
+  if (TW_LDS)
+    for (int e = threadIdx.x; e < L; e += kFftThreads) tw_lds[e] = reinterpret_cast<const C2<T>*>(a.tw)[e];
+  const C2<T>* tw = TW_LDS ? tw_lds : reinterpret_cast<const C2<T>*>(a.tw);
+  const int comp = int(blockIdx.x % unsigned(ncomp));
+  const int g1 = int(blockIdx.x / unsigned(ncomp)) * W;
+  const int o2 = blockIdx.y;
+  const C2<T>* in = reinterpret_cast<const C2<T>*>(a.in) + comp * a.comp_in;
+  C2<T>* out = reinterpret_cast<C2<T>*>(a.out) + comp * a.comp_out;
+  const int64_t in_o2 = boff(o2, a.in_o2, a.in_o2_hi, a.in_o2_sh);
+  const int64_t out_o2 = boff(o2, a.out_o2, a.out_o2_hi, a.out_o2_sh);
+  {
+    C2<T> v[PER];
+#pragma unroll
+    for (int p = 0; p < PER; ++p) {
+      const int e = threadIdx.x + p * kFftThreads, b = e % W, i = e / W, o1 = g1 + b;
+      v[p] = {T(0), T(0)};
+      if (o1 < a.n1 && i < a.n_in) v[p] = ld_stream(in + (o1 * a.in_o1 + in_o2 + boff(i, a.in_e, a.in_e_hi, a.in_e_sh)));
+    }
+#pragma unroll
+    for (int p = 0; p < PER; ++p) {
+      const int e = threadIdx.x + p * kFftThreads;
+      lds[pidx<L>(e % W, e / W)] = v[p];
+    }
+  }
+  __syncthreads();
+  fft_batch<T, L, ELEMS, false>(lds, tw);
+  // spectrum product: pair task t = (line b = t % W, kz = t / W), kz in [0, L/2]
+  {
+    const int m2 = o2 <= a.h_o2 ? o2 : 2 * a.h_o2 - o2;
+    const C2<T>* G = reinterpret_cast<const C2<T>*>(a.mul) + int64_t(m2) * a.mul_o2;
+    C2<T> gv[PG];
+#pragma unroll
+    for (int p = 0; p < PG; ++p) {
+      const int t = threadIdx.x + p * kFftThreads, b = t % W, kz = t / W, o1 = g1 + b;
+      const int m1 = o1 <= a.h_o1 ? o1 : 2 * a.h_o1 - o1;
+      gv[p] = {T(0), T(0)};
+      if (t < NPAIR && o1 < a.n1) gv[p] = G[int64_t(m1) * a.mul_o1 + int64_t(kz) * a.mul_e];
+    }
+#pragma unroll
+    for (int p = 0; p < PG; ++p) {
+      const int t = threadIdx.x + p * kFftThreads, b = t % W, kz = t / W;
+      if (t < NPAIR) {
+        lds[pidx<L>(b, kz)] = cmul(lds[pidx<L>(b, kz)], gv[p]);
+        if (kz > 0 && kz < L / 2) lds[pidx<L>(b, L - kz)] = cmul(lds[pidx<L>(b, L - kz)], gv[p]);
+      }
+    }
+  }
+  __syncthreads();
+  fft_batch<T, L, ELEMS, true>(lds, tw);
+#pragma unroll
+  for (int p = 0; p < PER; ++p) {
+    const int e = threadIdx.x + p * kFftThreads, b = e % W, i = e / W, o1 = g1 + b;
+    if (o1 < a.n1 && i < a.n_out)
+      st_stream(out + (o1 * a.out_o1 + out_o2 + boff(i, a.out_e, a.out_e_hi, a.out_e_sh)), lds[pidx<L>(b, i)]);
+  }
+}
+
+template <class T>
+void launch_zconv_L(int L, const PassArgs& a, int ncomp, hipStream_t s) {
+  constexpr int ELEMS = batch_elems<T, false>();
+  const size_t shm = size_t((ELEMS / L) * (L + L / 8 + 1) + (sizeof(T) == 4 ? L : 0)) * sizeof(C2<T>);
+  const int W = ELEMS / L;
+  dim3 grid(unsigned((a.n1 + W - 1) / W * ncomp), unsigned(a.n2), 1u);
+  switch (L) {
+#define SLIM_ZCONV_CASE(LL)                                                                                   \
+  case LL: {                                                                                                  \
+    static bool attr_set = false;                                                                             \
+    if (!attr_set) {                                                                                          \
+      SLIM_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fft_zconv<T, LL>),                        \
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, int(shm)));                     \
+      attr_set = true;                                                                                        \
+    }                                                                                                         \
+    hipLaunchKernelGGL((k_fft_zconv<T, LL>), grid, dim3(kFftThreads), shm, s, a, ncomp);                      \
+    break;                                                                                                    \
+  }
+    SLIM_ZCONV_CASE(16) SLIM_ZCONV_CASE(32) SLIM_ZCONV_CASE(64) SLIM_ZCONV_CASE(128) SLIM_ZCONV_CASE(256)
+    SLIM_ZCONV_CASE(512) SLIM_ZCONV_CASE(1024)
+#undef SLIM_ZCONV_CASE
+    default: throw Error(SLIM_E_UNSUPPORTED, "FFT length " + std::to_string(L) + " (2N must be a power of two in [16, 1024])");
+  }
+  SLIM_HIP(hipGetLastError());
 }
 
 template <class T, bool CONTIG, int MODE>
@@ -268,7 +347,7 @@ void launch_pass_L(int L, const PassArgs& a, int ncomp, hipStream_t s) {
 // Spectrum product of the layered medium on the full-z spectra of the four
 // components (lay: [comp][Z2][Y2][X2]), in place.  The reflected kernels depend on
 // z + z', so they multiply the source spectrum at -kz; each thread takes the pair
-// (kz, Z2 - kz) and writes both.  G^ (free space) is the even octant; the reflected
+// (kz, Z2 - kz) and writes both.  G^ (free space) is the even octant [ky][kz][kx]; the reflected
 // spectra cover kx <= Nx, ky <= Ny (mirrored; zx odd in x, zy odd in y) and all kz.
 template <class T>
 __global__ void k_layered_mix(C2<T>* S, int64_t comp, const C2<T>* gp, const C2<T>* rh, int64_t spec, int Nx, int Ny,
@@ -293,7 +372,7 @@ __global__ void k_layered_mix(C2<T>* S, int64_t comp, const C2<T>* gp, const C2<
   }
   auto product = [&](int kz, const C2<T>* self, const C2<T>* part, C2<T>* r) {
     const int mz = kz <= Nz ? kz : Z2 - kz;
-    const C2<T> g = gp[(int64_t(mz) * (Ny + 1) + my) * (Nx + 1) + mx];
+    const C2<T> g = gp[(int64_t(my) * (Nz + 1) + mz) * (Nx + 1) + mx];   // [ky][kz][kx]
     const int64_t ro = (int64_t(kz) * (Ny + 1) + my) * (Nx + 1) + mx;
     const C2<T> xx = rh[ro], zz = rh[spec + ro], ph = rh[2 * spec + ro];
     C2<T> zx = rh[3 * spec + ro], zy = rh[4 * spec + ro];
@@ -412,12 +491,12 @@ static void convolve_impl(Ctx& c, bool fp64, int ncomp, hipStream_t s, int comp0
       a.in = x2; a.out = x2;
       z_axis_in(a); z_axis_out(a); a.in_o1 = a.out_o1 = 1; a.in_o2 = a.out_o2 = YST;
       a.n1 = X2; a.n2 = Y2; a.n_in = Nz; a.n_out = Nz;
-      a.mul = fp64 ? c.d_ghat128.p : c.d_ghat64.p;
-      a.mul_e = int64_t(Nx + 1) * (Ny + 1); a.mul_o1 = 1; a.mul_o2 = Nx + 1;
+      a.mul = fp64 ? c.d_ghat128.p : c.d_ghat64.p;   // [ky][kz][kx]
+      a.mul_o1 = 1; a.mul_e = Nx + 1; a.mul_o2 = int64_t(Nx + 1) * (Nz + 1);
       a.h_e = Nz; a.h_o1 = Nx; a.h_o2 = Ny;
       a.comp_in = a.comp_out = CS2;
       a.tw = tw + tw_off(c, 2);
-      launch_pass_L<T, false, 2>(Z2, a, ncomp, s);
+      launch_zconv_L<T>(Z2, a, ncomp, s);
     } else {
       // layered z step: forward into the full-z work array, spectrum product with
       // the partner -kz, inverse back (keep z < Nz)

@@ -555,8 +555,11 @@ void build_precond(Ctx& c, hipStream_t s) {
                      std::to_string(plan.bytes()) + " bytes, budget " + std::to_string(budget));
   } else {
     bool found = false;
-    for (int64_t cap : {int64_t(0), int64_t(65536), int64_t(49152), int64_t(32768), int64_t(24576), int64_t(16384),
-                        int64_t(12288), int64_t(8192), int64_t(6144), int64_t(4096), int64_t(3072), int64_t(2048),
+    // the largest cap whose plan fits, on a ladder with steps of 1/8 to 1/4 (a small
+    // change of free memory moves the cap by one short step)
+    for (int64_t cap : {int64_t(0), int64_t(65536), int64_t(49152), int64_t(40960), int64_t(32768), int64_t(28672),
+                        int64_t(24576), int64_t(20480), int64_t(18432), int64_t(16384), int64_t(14336), int64_t(12288),
+                        int64_t(10240), int64_t(8192), int64_t(6144), int64_t(4096), int64_t(3072), int64_t(2048),
                         int64_t(1536), int64_t(1024), int64_t(768), int64_t(512)}) {
       Plan pl = make_plan(P, r, cap, overlap);
       if (o.verbose) {
