@@ -481,6 +481,34 @@ def srr_study(steps=50, warmup=5):
     out["mixed_vs_fp64_rel_err"] = {
         "y1": float(np.linalg.norm(ys["mixed"][:ne] - ys["fp64"][:ne]) / np.linalg.norm(ys["fp64"][:ne])),
         "y2": float(np.linalg.norm(ys["mixed"][ne:] - ys["fp64"][ne:]) / np.linalg.norm(ys["fp64"][ne:]))}
+    dense_entries = lay.internal_entries
+    ctx.close()
+    # the sparse interior form of the high-frequency regime: L_kc, K_kc summed over triangle
+    # pairs within three triangle diameters, Z~ kept on the RWG pairs they couple
+    v = mesh.verts[mesh.tris]
+    diam = float(np.max(np.linalg.norm(v - np.roll(v, 1, axis=1), axis=2)))
+    radius = 3.0 * diam
+    ctx = slim.Context(0)
+    ctx.set_mesh(mesh.verts, mesh.tris, mesh.obj, mesh.n_obj)
+    lay = ctx.build(freq=freq, grid=grid, precond=0, n_near=8, levels=6, n_r=8, n_t=10, hf_radius=radius)
+    sp = {"hf_radius_m": radius, "z_nnz": lay.z_nnz, "build_s": lay.build_seconds,
+          "z_fill": lay.z_nnz / (0.5 * dense_entries),
+          "internal_bytes_vs_dense_mixed": (lay.internal_entries * 8.0 + lay.z_nnz * 12.0) / (dense_entries * 8.0)}
+    for name, prec in (("mixed", slim.SLIM_MIXED), ("fp64", slim.SLIM_FP64)):
+        y = torch.zeros_like(x)
+        for _ in range(warmup):
+            ctx.matvec(prec, x, y)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(steps):
+            ctx.matvec(prec, x, y)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t) / steps
+        yy = y.cpu().numpy()
+        sp[name] = {"matvecs_per_s": 1.0 / dt, "ms_per_step": 1e3 * dt,
+                    "rel_diff_vs_dense_y1": float(np.linalg.norm(yy[:ne] - ys[name][:ne]) / np.linalg.norm(ys[name][:ne])),
+                    "rel_diff_vs_dense_y2": float(np.linalg.norm(yy[ne:] - ys[name][ne:]) / np.linalg.norm(ys[name][ne:]))}
+    out["sparse_interior"] = sp
     log("srr array: %s" % out)
     ctx.close()
     return out

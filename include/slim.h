@@ -120,6 +120,18 @@ typedef struct {
   const char* tune_cache; /* path of a text file of autotuning results keyed by
                              (kernel, shape, gfx950), read before and appended after
                              tuning; NULL = no cache                               */
+  /* Sparse interior operators at high frequency (Sec. III-A, point 3: with a small
+     skin depth L_kc and K_kc are treated as sparse by ignoring physically distant
+     interactions).  hf_radius > 0 (metres): the conductor-kernel operators L_kc, K_kc
+     of eq. (4) are summed over the triangle pairs whose centroids are at most
+     hf_radius apart (squared distance dx*dx + dy*dy + dz*dz <= r*r in FP64), Z~ =
+     -1/(j w eps_c) L~^-1 (K~ + I_x/2) is formed by an FP64 LU, and the product applies
+     it as a sparse matrix kept on the RWG pairs that share such a triangle pair
+     (entries elsewhere dropped); M_i = Y_eq,i Z~_i (Y_eq dense).  The internal arena
+     then holds only the M_i rows.  0 = dense interior operators (default).  The
+     conductor-block preconditioner is not built in this mode (precond must be 0,
+     else SLIM_E_UNSUPPORTED).                                                       */
+  double hf_radius;
 } slim_build_opts;
 
 /* Fill `o` with the defaults used by the tests (near_cheb 3, n_far 4, n_near 5,
@@ -137,7 +149,8 @@ typedef struct {
   int32_t grid[3];
   double grid_h[3], grid_origin[3];
   int64_t nnz_near_A, nnz_near_phi;    /* near-field CSR non-zeros               */
-  int64_t internal_entries;            /* sum_i 2 n_i^2                          */
+  int64_t internal_entries;            /* dense internal entries: sum_i 2 n_i^2
+                                          (sum_i n_i^2, the M_i rows, with hf_radius) */
   int64_t n_tiles;                     /* internal work-queue tiles              */
   int32_t slots;
   int32_t tile_rows;
@@ -149,6 +162,8 @@ typedef struct {
   int64_t precond_cap;                 /* cap in effect (0: every conductor whole) */
   int32_t fft_zblock;                  /* kernel shapes in effect (tuned or given) */
   int32_t rows_per_wave;
+  int64_t z_nnz;                       /* stored entries of the sparse Z~ (hf_radius > 0),
+                                          0 with dense interior operators           */
 } slim_layout;
 
 typedef struct {

@@ -87,6 +87,67 @@ std::vector<int32_t> near_candidates(const RWGTable& r, int64_t t0, int64_t t1, 
   return out;
 }
 
+// Pattern of the sparse Z~ of one object (edges [e0, e0 + n), triangles [t0, t1)):
+// local (row, column) pairs of RWGs that share a triangle pair whose centroids are at
+// most rad apart (squared distance dx*dx + dy*dy + dz*dz <= rad*rad, each product and
+// sum rounded on its own, as the device decides it), sorted by row then column.
+static void z_pattern(const RWGTable& r, int64_t t0, int64_t t1, int32_t e0, int32_t n, double rad,
+                      std::vector<int32_t>& rows, std::vector<int32_t>& cols) {
+#pragma clang fp contract(off)
+  std::vector<std::vector<int32_t>> adj(static_cast<size_t>(n));
+  double lo[3] = {1e300, 1e300, 1e300};
+  for (int64_t t = t0; t < t1; ++t)
+    for (int k = 0; k < 3; ++k) lo[k] = std::min(lo[k], r.centroid[3 * t + k]);
+  const double cell = rad;
+  auto key = [&](int64_t a, int64_t b, int64_t c) { return (a * 1000003 + b) * 1000003 + c; };
+  std::unordered_map<int64_t, std::vector<int32_t>> bins;
+  auto cell_of = [&](int64_t t, int64_t* c3) {
+    for (int k = 0; k < 3; ++k) c3[k] = int64_t(std::floor((r.centroid[3 * t + k] - lo[k]) / cell));
+  };
+  for (int64_t t = t0; t < t1; ++t) {
+    int64_t c3[3];
+    cell_of(t, c3);
+    bins[key(c3[0], c3[1], c3[2])].push_back(int32_t(t));
+  }
+  const double r2 = rad * rad;
+  for (int64_t t = t0; t < t1; ++t) {
+    int64_t c3[3];
+    cell_of(t, c3);
+    for (int64_t dz = -1; dz <= 1; ++dz)
+      for (int64_t dy = -1; dy <= 1; ++dy)
+        for (int64_t dx = -1; dx <= 1; ++dx) {
+          auto it = bins.find(key(c3[0] + dx, c3[1] + dy, c3[2] + dz));
+          if (it == bins.end()) continue;
+          for (int32_t u : it->second) {
+            if (u < t) continue;
+            const double ddx = r.centroid[3 * t] - r.centroid[3 * size_t(u)];
+            const double ddy = r.centroid[3 * t + 1] - r.centroid[3 * size_t(u) + 1];
+            const double ddz = r.centroid[3 * t + 2] - r.centroid[3 * size_t(u) + 2];
+            const double sx = ddx * ddx, sy = ddy * ddy, sz = ddz * ddz;
+            const double d2 = (sx + sy) + sz;
+            if (d2 > r2) continue;
+            for (int i = 0; i < 3; ++i)
+              for (int j = 0; j < 3; ++j) {
+                const int32_t m = r.tri_edge[3 * t + i] - e0, q = r.tri_edge[3 * size_t(u) + j] - e0;
+                adj[size_t(m)].push_back(q);
+                adj[size_t(q)].push_back(m);
+              }
+          }
+        }
+  }
+  rows.clear();
+  cols.clear();
+  for (int32_t m = 0; m < n; ++m) {
+    std::vector<int32_t>& a = adj[size_t(m)];
+    std::sort(a.begin(), a.end());
+    a.erase(std::unique(a.begin(), a.end()), a.end());
+    for (int32_t q : a) {
+      rows.push_back(m);
+      cols.push_back(q);
+    }
+  }
+}
+
 // I_x rows: entries with the (up to four) other edges of T+ and T- of each RWG.
 // The integrand (n x f_m).f_n is quadratic on a triangle; the three-edge-midpoint
 // rule with weights A/3 is exact.
@@ -184,13 +245,17 @@ Ctx::~Ctx() {
 static void build_internal(Ctx& c, hipStream_t s) {
   const RWGTable& r = c.rwg;
   RocHandle rh(s);
-  // arena layout
+  // arena layout: the 2n x ld rows of [Z_i; M_i] (rows padded to an even length,
+  // 16-byte aligned); with sparse interior operators only the n rows of M_i, and a
+  // block's offset is that of its (absent) row 0, so rows n..2n-1 sit where they would
+  const bool hf = c.opts.hf_radius > 0.0;
   c.blocks.resize(r.n_obj);
   int64_t off = 0, nmax = 0;
   for (int i = 0; i < r.n_obj; ++i) {
     int64_t n = r.obj_edge_off[i + 1] - r.obj_edge_off[i];
-    c.blocks[i] = {off, int32_t(n), int32_t(r.obj_edge_off[i])};
-    off += 2 * n * ((n + 1) & ~int64_t(1));   // rows padded to an even length (16-byte aligned)
+    const int64_t ld = (n + 1) & ~int64_t(1);
+    c.blocks[i] = {hf ? off - n * ld : off, int32_t(n), int32_t(r.obj_edge_off[i])};
+    off += (hf ? 1 : 2) * n * ld;
     nmax = std::max(nmax, n);
   }
   c.arena_elems = off;
@@ -215,6 +280,28 @@ static void build_internal(Ctx& c, hipStream_t s) {
   L.nrm = c.d_nrm.as<double>(); L.area = c.d_area.as<double>(); L.diam = c.d_diam.as<double>();
   L.tri_edge = c.d_tri_edge.as<int32_t>(); L.tri_sign = c.d_tri_sign.as<int8_t>(); L.len = c.d_len.as<double>();
   DevBuf d_pairs;
+  // sparse Z~ (hf_radius > 0): CSR over all RWG rows, global columns; per object the
+  // local (row, column) list gathers its entries from the dense FP64 solution
+  std::vector<int64_t> zs_ptr(1, 0);
+  std::vector<int32_t> zs_col;
+  DevBuf d_zrow, d_zcol, d_zval;
+  if (hf) {
+    c.d_zs_hi.release();
+    c.d_zs_lo.release();
+  }
+  std::vector<std::vector<int32_t>> z_rows(hf ? r.n_obj : 0), z_cols(hf ? r.n_obj : 0);
+  int64_t z_total = 0;
+  for (int i = 0; hf && i < r.n_obj; ++i) {
+    z_pattern(r, r.obj_tri_off[i], r.obj_tri_off[i + 1], c.blocks[i].e0, c.blocks[i].n, c.opts.hf_radius, z_rows[i],
+              z_cols[i]);
+    z_total += int64_t(z_rows[i].size());
+  }
+  if (hf) {
+    SLIM_REQUIRE(z_total < (int64_t(1) << 40), SLIM_E_UNSUPPORTED, "sparse interior operator too large");
+    c.d_zs_hi.alloc(size_t(std::max<int64_t>(1, z_total)) * sizeof(Cplx<float>));
+    c.d_zs_lo.alloc(size_t(std::max<int64_t>(1, z_total)) * sizeof(Cplx<float>));
+  }
+  int64_t z_done = 0;
   for (int i = 0; i < r.n_obj; ++i) {
     const int n = c.blocks[i].n;
     const size_t bytes = size_t(n) * n * 16;
@@ -232,13 +319,32 @@ static void build_internal(Ctx& c, hipStream_t s) {
     L.k = c.kc[i];
     L.Lk = bufL.as<double>(); L.Kk = bufZ.as<double>(); L.Lvec = nullptr; L.Lphi = nullptr;
     L.skip_mag = 1e-24;   // conductor kernel: far pairs with |e^{-jk R}| < 1e-24 contribute nothing
+    L.cut_r2 = hf ? c.opts.hf_radius * c.opts.hf_radius : 0.0;   // sparse L~, K~: distant pairs ignored
     launch_assemble(L, s);
+    L.cut_r2 = 0.0;
     launch_add_scaled_ix(bufZ.as<double>(), c.d_ix_col.as<int32_t>(), c.d_ix_val.as<double>(), L.e0, n, 0.5, s);
     SLIM_ROC(rocsolver_zgetrf(rh.h, n, n, reinterpret_cast<rocblas_double_complex*>(bufL.p), n,
                               ipiv.as<rocblas_int>(), info.as<rocblas_int>() + 2 * i));
     lu_solve(rh.h, n, bufL.as<double>(), ipiv.as<rocblas_int>(), bufZ.as<double>(), s);
     cd fz = -1.0 / (cd(0.0, 1.0) * c.omega * c.epsc[i]);
     launch_scale(bufZ.as<double>(), int64_t(n) * n, fz, s);
+    if (hf) {
+      // keep Z~ on its pattern: gather the entries (complex64 hi + lo, global columns),
+      // then zero the dense copy off the pattern for M = Y_eq Z~
+      const int64_t nz = int64_t(z_rows[i].size());
+      d_zrow.upload(z_rows[i]);
+      d_zcol.upload(z_cols[i]);
+      if (d_zval.bytes < size_t(std::max<int64_t>(1, nz)) * 16) d_zval.alloc(size_t(std::max<int64_t>(1, nz)) * 16);
+      launch_z_gather_mask(bufZ.as<double>(), n, d_zrow.as<int32_t>(), d_zcol.as<int32_t>(), nz, d_zval.as<double>(),
+                           c.d_zs_hi.as<Cplx<float>>() + z_done, c.d_zs_lo.as<Cplx<float>>() + z_done, s);
+      for (int64_t k = 0; k < nz; ++k) zs_col.push_back(c.blocks[i].e0 + z_cols[i][size_t(k)]);
+      int64_t k = 0;
+      for (int m = 0; m < n; ++m) {
+        while (k < nz && z_rows[i][size_t(k)] == m) ++k;
+        zs_ptr.push_back(z_done + k);
+      }
+      z_done += nz;
+    }
     // ---- Y_eq,i = 1/(j w mu0) L_k0^{-1} (K_k0 + I_x/2)  (eq. (5), free-space layer) ----
     SLIM_HIP(hipMemsetAsync(bufL.p, 0, bytes, s));
     SLIM_HIP(hipMemsetAsync(bufB.p, 0, bytes, s));
@@ -257,8 +363,10 @@ static void build_internal(Ctx& c, hipStream_t s) {
                            reinterpret_cast<rocblas_double_complex*>(bufB.p), n,
                            reinterpret_cast<rocblas_double_complex*>(bufZ.p), n, &beta,
                            reinterpret_cast<rocblas_double_complex*>(bufL.p), n));
-    launch_pack_block(bufZ.as<double>(), bufL.as<double>(), n, c.d_hi.as<Cplx<float>>() + c.blocks[i].off,
-                      c.d_lo.as<Cplx<float>>() + c.blocks[i].off, s);
+    const int64_t row0 = hf ? n : 0;   // sparse mode: only the rows of M_i are stored
+    const int64_t first = c.blocks[i].off + row0 * ((n + 1) & ~1);
+    launch_pack_block(bufZ.as<double>(), bufL.as<double>(), n, int(row0), c.d_hi.as<Cplx<float>>() + first,
+                      c.d_lo.as<Cplx<float>>() + first, s);
     SLIM_HIP(hipStreamSynchronize(s));   // the pair list of the next object reuses d_pairs
     if (c.opts.verbose) {
       static thread_local auto last = std::chrono::steady_clock::now();
@@ -275,6 +383,19 @@ static void build_internal(Ctx& c, hipStream_t s) {
   for (int i = 0; i < 2 * r.n_obj; ++i)
     SLIM_REQUIRE(h_info[i] == 0, SLIM_E_NUMERIC,
                  "singular interior matrix of object " + std::to_string(i / 2) + (i % 2 ? " (L_k0)" : " (L_kc)"));
+  c.hf_sparse = hf;
+  c.z_nnz = hf ? z_total : 0;
+  if (hf) {
+    SLIM_REQUIRE(int64_t(zs_ptr.size()) == r.n_e + 1 && zs_ptr.back() == z_total, SLIM_E_STATE,
+                 "sparse interior operator: row pointers do not cover the edges");
+    c.d_zs_ptr.upload(zs_ptr);
+    c.d_zs_col.upload(zs_col);
+  } else {
+    c.d_zs_ptr.release();
+    c.d_zs_col.release();
+    c.d_zs_hi.release();
+    c.d_zs_lo.release();
+  }
 }
 
 static void build_plain_external(Ctx& c, hipStream_t s) {
@@ -420,6 +541,9 @@ void build_all(Ctx& c, const slim_build_opts& o) {
   SLIM_REQUIRE(o.internal_kernel == 0, SLIM_E_UNSUPPORTED,
                "internal_kernel: only the FP32-FMA GEMV (0) is built; a split-BF16 MFMA kernel would read the same "
                "bytes at one right-hand side");
+  SLIM_REQUIRE(std::isfinite(o.hf_radius) && o.hf_radius >= 0.0, SLIM_E_ARG, "hf_radius must be finite and >= 0");
+  SLIM_REQUIRE(!(o.hf_radius > 0.0 && o.precond), SLIM_E_UNSUPPORTED,
+               "the conductor-block preconditioner needs the dense Z_i rows: build with precond = 0 when hf_radius > 0");
   SLIM_HIP(hipSetDevice(c.device));
   c.built = false;
   // A new build starts in free space: the reflected kernels, their spectra and the
@@ -550,6 +674,7 @@ void build_all(Ctx& c, const slim_build_opts& o) {
   Lo.precond_cap = c.pc_cap;
   Lo.fft_zblock = c.plain ? 0 : 1 << c.fft_zsh;
   Lo.rows_per_wave = c.rw_mixed;
+  Lo.z_nnz = c.z_nnz;
   c.built = true;
 }
 

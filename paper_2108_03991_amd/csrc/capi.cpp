@@ -60,6 +60,7 @@ void slim_default_build_opts(slim_build_opts* o) {
   o->fft_zblock = 0;
   o->rows_per_wave = 0;
   o->tune_cache = nullptr;
+  o->hf_radius = 0.0;
 }
 
 slim_status slim_create(int32_t hip_device, slim_ctx** out) {

@@ -61,6 +61,12 @@ struct Ctx {
   DevBuf d_blocks;                      // Block[]
   int64_t arena_elems = 0;
 
+  // ---- sparse Z~ of the high-frequency form (hf_radius > 0): CSR over all RWG rows,
+  //      global columns, hi and lo complex64 values; the arena then holds only M_i ----
+  bool hf_sparse = false;
+  int64_t z_nnz = 0;
+  DevBuf d_zs_ptr, d_zs_col, d_zs_hi, d_zs_lo;
+
   // ---- work queues of the persistent internal kernel ----
   std::vector<Tile> tiles;              // grouped by slot
   std::vector<int32_t> slot_start;      // slots+1
@@ -183,7 +189,13 @@ double time_internal(Ctx& c, int reps);   // ms per launch of the mixed internal
 double time_product(Ctx& c, int reps);    // ms per mixed product
 void launch_cast_c128_to_c64(const void* in, void* out, int64_t n, hipStream_t s);
 void launch_cast_c64_to_c128(const void* in, void* out, int64_t n, hipStream_t s);
-void launch_pack_block(const double* Zcm, const double* Mcm, int n, Cplx<float>* hi, Cplx<float>* lo, hipStream_t s);
+// rows [row0, 2n) of [Z; M] (column-major n x n inputs) -> hi / lo, row-major, rows padded to even length
+void launch_pack_block(const double* Zcm, const double* Mcm, int n, int row0, Cplx<float>* hi, Cplx<float>* lo,
+                       hipStream_t s);
+// sparse Z~: vals[k] = Z[rows[k] + cols[k] n] (column-major n x n) for k < nnz, hi / lo of
+// them, and Z zeroed everywhere else
+void launch_z_gather_mask(double* Zcm, int n, const int32_t* rows, const int32_t* cols, int64_t nnz, double* vals,
+                          Cplx<float>* hi, Cplx<float>* lo, hipStream_t s);
 void launch_add_scaled_ix(double* B, const int32_t* ix_col, const double* ix_val, int e0, int n, double half, hipStream_t s);
 void launch_scale(double* M, int64_t n_elems, cd f, hipStream_t s);
 void launch_usolve_block(const double* U, int64_t ld, int i0, int nb, double* X, int64_t ldx, int nrhs, hipStream_t s);

@@ -50,11 +50,12 @@ __global__ void k_c64_to_c128(const float2* in, double2* out, int64_t n) {
 // ---------------------------------------------------------------------------
 // Column-major complex128 Z and M (n x n) -> rows of the stacked row-major block
 // [Z; M] with leading dimension ld, split into hi = fl32(v), lo = fl32(v - hi).
-__global__ void k_pack_block(const double2* Z, const double2* M, int n, int ld, float2* hi, float2* lo) {
+// rows [row0, 2n) of [Z; M]: element i of the output is row row0 + i / ld, column i % ld
+__global__ void k_pack_block(const double2* Z, const double2* M, int n, int row0, int ld, float2* hi, float2* lo) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  const int64_t tot = int64_t(2 * n) * ld;
+  const int64_t tot = int64_t(2 * n - row0) * ld;
   if (i >= tot) return;
-  const int row = int(i / ld), col = int(i % ld);
+  const int row = row0 + int(i / ld), col = int(i % ld);
   double2 v = make_double2(0.0, 0.0);
   if (col < n) v = row < n ? Z[row + int64_t(col) * n] : M[(row - n) + int64_t(col) * n];
   float2 h = make_float2(float(v.x), float(v.y));
@@ -69,6 +70,25 @@ __global__ void k_pack_dense(const double2* A, int64_t n, float2* hi, float2* lo
   float2 h = make_float2(float(v.x), float(v.y));
   hi[i] = h;
   lo[i] = make_float2(float(v.x - double(h.x)), float(v.y - double(h.y)));
+}
+
+// Sparse Z~: the entries on the pattern (local rows / columns of a column-major n x n
+// matrix), in FP64 and as complex64 hi + lo; and back into a zeroed dense copy.
+__global__ void k_z_gather(const double2* Z, int n, const int32_t* rows, const int32_t* cols, int64_t nnz,
+                           double2* vals, float2* hi, float2* lo) {
+  const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (k >= nnz) return;
+  const double2 v = Z[rows[k] + int64_t(cols[k]) * n];
+  vals[k] = v;
+  const float2 h = make_float2(float(v.x), float(v.y));
+  hi[k] = h;
+  lo[k] = make_float2(float(v.x - double(h.x)), float(v.y - double(h.y)));
+}
+__global__ void k_z_scatter(double2* Z, int n, const int32_t* rows, const int32_t* cols, int64_t nnz,
+                            const double2* vals) {
+  const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (k >= nnz) return;
+  Z[rows[k] + int64_t(cols[k]) * n] = vals[k];
 }
 
 // B (column-major n x n, local RWG indices) += half * I_x
@@ -291,8 +311,13 @@ __global__ void __launch_bounds__(256) k_internal(const float2* __restrict__ hi,
 // product is four real ones, Re = Ar Hr - Ai Hi, Im = Ar Hi + Ai Hr: 12 MFMAs per 32
 // columns of A per 16 right-hand sides.
 // Operand layout of the 16x16x32 MFMA in a wave: lane l holds row (l & 15) of A and
-// column (l & 15) of B, each at K = 8 (l >> 4) ... + 7; the result gives lane l
-// column (l & 15), rows 4 (l >> 4) ... + 3.
+// column (l & 15) of B, each at eight K slots; the result gives lane l column (l & 15),
+// rows 4 (l >> 4) ... + 3.  The sum runs over K in any order that A and B share, so
+// the slots of lane group g = l >> 4 are taken as the column pairs 8 p + 2 g, + 1
+// (p = 0..3) of a 32-column chunk: in each 16-byte load the four lane groups of a row
+// read 64 contiguous bytes.  The split planes of H are stored chunk by chunk, each
+// chunk as [column][32 K slots] in that order: a lane's eight values are contiguous,
+// and the 64 lanes of a column group read one contiguous kilobyte.
 // ---------------------------------------------------------------------------
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -307,11 +332,12 @@ __device__ __forceinline__ void split_bf16(const float* v, bf16x8& hi, bf16x8& l
 }
 
 // H (complex128, the first ne entries of the columns of X, leading dimension nsys)
-// -> the complex64 copy H64 [R][ne] and the four split planes Hs[p][col][ldh]
-// (p: re hi, re lo, im hi, im lo).  In a plane, block i starts at a multiple of
-// eight (hpos maps an edge to its position), so that the MFMA kernel's 16-byte
-// loads are aligned; the gaps between blocks stay zero from the allocation.
-__global__ void k_split_h(const double2* X, int64_t nsys, int64_t ne, int R, int64_t ldh, int64_t plane,
+// -> the complex64 copy H64 [R][ne] and the four split planes (re hi, re lo, im hi,
+// im lo), each [chunk][column (ncol)][32].  Block i occupies whole 32-entry chunks
+// (hpos maps an edge to chunk * 32 + slot, the slot in the MFMA kernel's K order), so
+// that the kernel's 16-byte loads are aligned and contiguous; the entries past n_i
+// stay zero from the allocation.
+__global__ void k_split_h(const double2* X, int64_t nsys, int64_t ne, int R, int ncol, int64_t plane,
                           const int32_t* hpos, float2* H64, __bf16* Hs) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= int64_t(R) * ne) return;
@@ -320,7 +346,8 @@ __global__ void k_split_h(const double2* X, int64_t nsys, int64_t ne, int R, int
   const double2 v = X[int64_t(col) * nsys + k];
   const float re = float(v.x), im = float(v.y);
   H64[i] = make_float2(re, im);
-  const int64_t o = int64_t(col) * ldh + hpos[k];
+  const int32_t hp = hpos[k];
+  const int64_t o = (int64_t(hp >> 5) * ncol + col) * 32 + (hp & 31);
   const __bf16 rh = __bf16(re), ih = __bf16(im);
   Hs[o] = rh;
   Hs[plane + o] = __bf16(re - float(rh));
@@ -328,15 +355,17 @@ __global__ void k_split_h(const double2* X, int64_t nsys, int64_t ne, int R, int
   Hs[3 * plane + o] = __bf16(im - float(ih));
 }
 
-// One wave computes RG 16-row groups x NCG 16-column groups: the H fragments of a K
-// chunk are loaded once for the RG row groups, the next chunk's A and H fragments are
-// loaded while the current chunk's MFMAs run, and the 12 products of a chunk are issued
-// term by term across all accumulators, so that dependent MFMAs are far apart.
+// One wave computes RG 16-row groups x NCG 16-column groups.  The next K chunk's A
+// fragments (HBM) are loaded while the current chunk's MFMAs run; the H fragments of a
+// column group (L2-resident, one contiguous kilobyte per load) are read just before
+// their products, so that few registers are held across the loop and several waves fit
+// a SIMD.  Within a column group the 12 products are issued term by term over the four
+// accumulators, so that dependent MFMAs are four apart.
 template <int NCG, int RG>
 __global__ void __launch_bounds__(256) k_internal_mfma(const float2* __restrict__ hi, const BlockDev* __restrict__ blocks,
                                                        const TileQueue q0, const TileQueue q1,
                                                        const int64_t* __restrict__ hoff, const __bf16* __restrict__ Hs,
-                                                       int64_t plane, int64_t ldh,
+                                                       int64_t plane, int ldc, int col0,
                                                        const float2* __restrict__ H64, int64_t ne, int ncol,
                                                        float2* __restrict__ E, float2* __restrict__ J) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -367,31 +396,16 @@ __global__ void __launch_bounds__(256) k_internal_mfma(const float2* __restrict_
           const float2* arow = hi + B.off + int64_t(row) * ld;
 #pragma unroll
           for (int p = 0; p < 4; ++p) {
-            const int kk = k0 + 8 * lg + 2 * p;
+            const int kk = k0 + 8 * p + 2 * lg;
             a[r][p] = (row < rend && kk < ld) ? ntload(arow + kk) : make_float4(0.f, 0.f, 0.f, 0.f);
           }
         }
       };
-      // H fragments of the K chunk at k0: four split planes per column group
-      auto load_h = [&](int k0, bf16x8 (*h)[4]) {
-        const int64_t kb = h0 + k0 + 8 * lg;
-#pragma unroll
-        for (int g = 0; g < NCG; ++g) {
-          const int64_t o = int64_t(16 * g + lr) * ldh + kb;
-#pragma unroll
-          for (int pl = 0; pl < 4; ++pl) h[g][pl] = *reinterpret_cast<const bf16x8*>(Hs + pl * plane + o);
-        }
-      };
       float4 a_cur[RG][4], a_nxt[RG][4];
-      bf16x8 h_cur[NCG][4], h_nxt[NCG][4];
       load_a(0, a_cur);
-      load_h(0, h_cur);
       for (int k0 = 0; k0 < n; k0 += 32) {
         const bool more = k0 + 32 < n;
-        if (more) {
-          load_a(k0 + 32, a_nxt);
-          load_h(k0 + 32, h_nxt);
-        }
+        if (more) load_a(k0 + 32, a_nxt);
         bf16x8 ah[RG][2], al[RG][2];   // [r][0]: real part, [r][1]: imaginary part
 #pragma unroll
         for (int r = 0; r < RG; ++r) {
@@ -404,31 +418,33 @@ __global__ void __launch_bounds__(256) k_internal_mfma(const float2* __restrict_
           split_bf16(re, ah[r][0], al[r][0]);
           split_bf16(im, ah[r][1], al[r][1]);
         }
+        const int64_t cb = ((h0 + k0) >> 5) * ldc + col0;     // chunk of K, first column
         // accumulators: 0 = Ar Hr, 1 = Ai Hi, 2 = Ar Hi, 3 = Ai Hr; planes: 0 Hr hi, 1 Hr lo, 2 Hi hi, 3 Hi lo
         // term 0: a_hi b_hi, term 1: a_hi b_lo, term 2: a_lo b_hi
 #pragma unroll
-        for (int term = 0; term < 3; ++term)
+        for (int g = 0; g < NCG; ++g) {
+          bf16x8 hv[4];
+          const int64_t o = (cb + 16 * g + lr) * 32 + 8 * lg;
 #pragma unroll
-          for (int r = 0; r < RG; ++r)
+          for (int pl = 0; pl < 4; ++pl) hv[pl] = *reinterpret_cast<const bf16x8*>(Hs + pl * plane + o);
 #pragma unroll
-            for (int g = 0; g < NCG; ++g)
+          for (int term = 0; term < 3; ++term)
+#pragma unroll
+            for (int r = 0; r < RG; ++r)
 #pragma unroll
               for (int q = 0; q < 4; ++q) {
                 const int ai = (q == 0 || q == 2) ? 0 : 1;     // Ar for accumulators 0, 2; Ai for 1, 3
                 const int bp = (q == 0 || q == 3) ? 0 : 2;     // Hr for accumulators 0, 3; Hi for 1, 2
                 const bf16x8 av = term == 2 ? al[r][ai] : ah[r][ai];
-                const bf16x8 bv = term == 1 ? h_cur[g][bp + 1] : h_cur[g][bp];
+                const bf16x8 bv = term == 1 ? hv[bp + 1] : hv[bp];
                 acc[r][g][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[r][g][q], 0, 0, 0);
               }
+        }
         if (more) {
 #pragma unroll
           for (int r = 0; r < RG; ++r)
 #pragma unroll
             for (int p = 0; p < 4; ++p) a_cur[r][p] = a_nxt[r][p];
-#pragma unroll
-          for (int g = 0; g < NCG; ++g)
-#pragma unroll
-            for (int pl = 0; pl < 4; ++pl) h_cur[g][pl] = h_nxt[g][pl];
         }
       }
       // epilogue: e rows (row < n) and j = H - g rows (row >= n), column 16 g + lr
@@ -671,6 +687,38 @@ __global__ void k_copy_out(const void* in, double2* out, int64_t n) {
   out[i] = make_double2(double(v.x), double(v.y));
 }
 
+// e = Z~ H with the sparse Z~ of the high-frequency form (CSR over all RWG rows, global
+// columns, complex64 hi + lo values; FP64 adds lo).  Eight lanes per row stride its
+// entries; the partial sums meet through lane shuffles.
+template <bool F64>
+__global__ void __launch_bounds__(256) k_zsparse(const int64_t* __restrict__ ptr, const int32_t* __restrict__ col,
+                                                 const float2* __restrict__ vhi, const float2* __restrict__ vlo,
+                                                 const void* __restrict__ Hv, void* __restrict__ ev, int64_t n) {
+  using T = typename P<F64>::T;
+  const C2<T>* H = reinterpret_cast<const C2<T>*>(Hv);
+  C2<T>* e = reinterpret_cast<C2<T>*>(ev);
+  const int64_t row = (int64_t(blockIdx.x) * 256 + threadIdx.x) >> 3;
+  const int sub = threadIdx.x & 7;
+  T sr = 0, si = 0;
+  if (row < n) {
+    for (int64_t k = ptr[row] + sub; k < ptr[row + 1]; k += 8) {
+      const C2<T> h = H[col[k]];
+      const float2 a = vhi[k];
+      T ar = a.x, ai = a.y;
+      if (F64) {
+        const float2 b = vlo[k];
+        ar += T(b.x);
+        ai += T(b.y);
+      }
+      sr += ar * h.x - ai * h.y;
+      si += ar * h.y + ai * h.x;
+    }
+  }
+  sr = group_sum8<F64>(sr);
+  si = group_sum8<F64>(si);
+  if (sub == 0 && row < n) e[row] = {sr, si};
+}
+
 // Work list of a phase of the internal tiles (0: rows of M_i, 1: rows of Z_i) on
 // dynamic-dispatch counter `ctr` (used in the dynamic scheduling modes).
 TileQueue phase_queue(Ctx& c, int phase, int ctr) {
@@ -690,6 +738,14 @@ void internal_launch(Ctx& c, const void* H, void* e, void* j, void* g, hipStream
   if (phase < 0) {
     internal_launch<F64>(c, H, e, j, g, s, 0);
     internal_launch<F64>(c, H, e, j, g, s, 1);
+    return;
+  }
+  if (phase == 1 && c.hf_sparse) {
+    // rows of Z~: the sparse product of the high-frequency form
+    const int64_t ne = c.rwg.n_e;
+    hipLaunchKernelGGL(k_zsparse<F64>, dim3(nblk(8 * ne)), dim3(256), 0, s, c.d_zs_ptr.as<int64_t>(),
+                       c.d_zs_col.as<int32_t>(), c.d_zs_hi.as<float2>(), c.d_zs_lo.as<float2>(), H, e, ne);
+    SLIM_HIP(hipGetLastError());
     return;
   }
   unsigned long long* st = c.record ? c.d_stamps.as<unsigned long long>() : nullptr;
@@ -840,13 +896,28 @@ void launch_cast_c64_to_c128(const void* in, void* out, int64_t n, hipStream_t s
                      reinterpret_cast<double2*>(out), n);
   SLIM_HIP(hipGetLastError());
 }
-void launch_pack_block(const double* Z, const double* M, int n, Cplx<float>* hi, Cplx<float>* lo, hipStream_t s) {
+void launch_pack_block(const double* Z, const double* M, int n, int row0, Cplx<float>* hi, Cplx<float>* lo,
+                       hipStream_t s) {
   const int ld = (n + 1) & ~1;
-  const int64_t tot = int64_t(2 * n) * ld;
+  const int64_t tot = int64_t(2 * n - row0) * ld;
   hipLaunchKernelGGL(k_pack_block, dim3(nblk(tot)), dim3(256), 0, s, reinterpret_cast<const double2*>(Z),
-                     reinterpret_cast<const double2*>(M), n, ld, reinterpret_cast<float2*>(hi),
+                     reinterpret_cast<const double2*>(M), n, row0, ld, reinterpret_cast<float2*>(hi),
                      reinterpret_cast<float2*>(lo));
   SLIM_HIP(hipGetLastError());
+}
+void launch_z_gather_mask(double* Z, int n, const int32_t* rows, const int32_t* cols, int64_t nnz, double* vals,
+                          Cplx<float>* hi, Cplx<float>* lo, hipStream_t s) {
+  if (nnz > 0) {
+    hipLaunchKernelGGL(k_z_gather, dim3(nblk(nnz)), dim3(256), 0, s, reinterpret_cast<const double2*>(Z), n, rows, cols,
+                       nnz, reinterpret_cast<double2*>(vals), reinterpret_cast<float2*>(hi), reinterpret_cast<float2*>(lo));
+    SLIM_HIP(hipGetLastError());
+  }
+  SLIM_HIP(hipMemsetAsync(Z, 0, size_t(n) * n * 16, s));
+  if (nnz > 0) {
+    hipLaunchKernelGGL(k_z_scatter, dim3(nblk(nnz)), dim3(256), 0, s, reinterpret_cast<double2*>(Z), n, rows, cols, nnz,
+                       reinterpret_cast<const double2*>(vals));
+    SLIM_HIP(hipGetLastError());
+  }
 }
 void launch_pack_dense(const double* A, int64_t rows, int64_t cols, Cplx<float>* hi, Cplx<float>* lo, hipStream_t s) {
   const int64_t n = rows * cols;
@@ -929,6 +1000,7 @@ void matvec_graph(Ctx& c, slim_prec prec, const void* x, void* y, hipStream_t s)
   // per phase: first workgroup start to last workgroup end
   unsigned long long a0 = ~0ull, a1 = 0;
   for (int ph = 0; ph < 2; ++ph) {
+    if (c.phase_count[ph] == 0) continue;   // no persistent launch (the sparse Z~ rows)
     unsigned long long t0 = ~0ull, t1 = 0;
     for (int k = 0; k < c.slots; ++k) {
       t0 = std::min(t0, st[2 * (size_t(ph) * c.slots + k)]);
@@ -1009,14 +1081,19 @@ void matvec_block(Ctx& c, slim_prec prec, const void* X, void* Y, int R, hipStre
   }
   const int Rpad = (R + 15) & ~15;
   if (c.blk_ldh == 0) {
-    // aligned H slices: block i occupies round_up(n_i, 8) + 32 entries of a plane column
+    // block i occupies round_up(n_i, 32) / 32 chunks of the planes; local index k sits
+    // in chunk k / 32 at the slot of its K position (column pair 8 p + 2 g + e ->
+    // slot 8 g + 2 p + e); hpos = chunk * 32 + slot
     std::vector<int64_t> hoff(c.blocks.size());
     std::vector<int32_t> hpos(ne);
     int64_t o = 0;
     for (size_t i = 0; i < c.blocks.size(); ++i) {
       hoff[i] = o;
-      for (int k = 0; k < c.blocks[i].n; ++k) hpos[c.blocks[i].e0 + k] = int32_t(o + k);
-      o += ((c.blocks[i].n + 7) & ~7) + 32;
+      for (int k = 0; k < c.blocks[i].n; ++k) {
+        const int kk = k & 31, p = kk >> 3, g = (kk >> 1) & 3, e = kk & 1;
+        hpos[c.blocks[i].e0 + k] = int32_t(o + (k & ~31) + 8 * g + 2 * p + e);
+      }
+      o += (c.blocks[i].n + 31) & ~31;
     }
     SLIM_REQUIRE(o < (int64_t(1) << 31), SLIM_E_UNSUPPORTED, "too many unknowns for the block product");
     c.d_blk_hoff.upload(hoff);
@@ -1034,7 +1111,7 @@ void matvec_block(Ctx& c, slim_prec prec, const void* X, void* Y, int R, hipStre
   const int64_t plane = int64_t(c.blk_cols) * c.blk_ldh;
   __bf16* Hs = c.d_blk_hs.as<__bf16>();
   hipLaunchKernelGGL(k_split_h, dim3(nblk(int64_t(R) * ne)), dim3(256), 0, s, reinterpret_cast<const double2*>(X), nsys,
-                     ne, R, c.blk_ldh, plane, c.d_blk_hpos.as<int32_t>(), c.d_blk_h64.as<float2>(), Hs);
+                     ne, R, c.blk_cols, plane, c.d_blk_hpos.as<int32_t>(), c.d_blk_h64.as<float2>(), Hs);
   SLIM_HIP(hipGetLastError());
   if (c.prof_on) c.prof_mark(0, s);
   for (int col0 = 0; col0 < R; col0 += 64) {
@@ -1042,15 +1119,22 @@ void matvec_block(Ctx& c, slim_prec prec, const void* X, void* Y, int R, hipStre
     auto go = [&](auto kern) {
       hipLaunchKernelGGL(kern, dim3(unsigned(c.slots)), dim3(256), 0, s, c.d_hi.as<float2>(), c.d_blocks.as<BlockDev>(),
                          phase_queue(c, 0, 2), phase_queue(c, 1, 3), c.d_blk_hoff.as<int64_t>(),
-                         Hs + int64_t(col0) * c.blk_ldh, plane, c.blk_ldh, c.d_blk_h64.as<float2>() + int64_t(col0) * ne,
+                         Hs, plane, c.blk_cols, col0, c.d_blk_h64.as<float2>() + int64_t(col0) * ne,
                          ne, ncol, c.d_blk_e.as<float2>() + int64_t(col0) * ne, c.d_blk_j.as<float2>() + int64_t(col0) * ne);
     };
-    if (ncg == 1) go(k_internal_mfma<1, 2>);
-    else if (ncg == 2) go(k_internal_mfma<2, 2>);
+    if (ncg == 1) go(k_internal_mfma<1, 1>);
+    else if (ncg == 2) go(k_internal_mfma<2, 1>);
     else if (ncg == 3) go(k_internal_mfma<3, 1>);
     else go(k_internal_mfma<4, 1>);
     SLIM_HIP(hipGetLastError());
   }
+  if (c.hf_sparse)   // the rows of Z~ column by column (sparse, not on the matrix cores)
+    for (int col = 0; col < R; ++col) {
+      hipLaunchKernelGGL(k_zsparse<false>, dim3(nblk(8 * ne)), dim3(256), 0, s, c.d_zs_ptr.as<int64_t>(),
+                         c.d_zs_col.as<int32_t>(), c.d_zs_hi.as<float2>(), c.d_zs_lo.as<float2>(),
+                         c.d_blk_h64.as<float2>() + int64_t(col) * ne, c.d_blk_e.as<float2>() + int64_t(col) * ne, ne);
+      SLIM_HIP(hipGetLastError());
+    }
   if (c.prof_on) c.prof_mark(0, s);
   for (int col = 0; col < R; ++col)
     matvec_t<false>(c, Xc + size_t(col) * nsys * 16, Yc + size_t(col) * nsys * 16, nullptr, nullptr, nullptr, nullptr, s,

@@ -213,6 +213,17 @@ __device__ __forceinline__ bool pair_is_near(const double* cen, const double* di
   return d2 < __dmul_rn(dm, dm);
 }
 
+// A pair farther apart than the cutoff of the sparse interior operators (squared
+// centroid distance summed as dx*dx + dy*dy + dz*dz, no contracted multiply-adds).
+__device__ __forceinline__ bool pair_beyond(const double* cen, int t, int u, double cut_r2) {
+  if (cut_r2 <= 0.0) return false;
+  double dx = __dsub_rn(cen[3 * t], cen[3 * u]);
+  double dy = __dsub_rn(cen[3 * t + 1], cen[3 * u + 1]);
+  double dz = __dsub_rn(cen[3 * t + 2], cen[3 * u + 2]);
+  double d2 = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
+  return d2 > cut_r2;
+}
+
 __device__ __forceinline__ bool pair_is_coplanar(const double* cen, const double* nrm, const double* diam, int t, int u) {
   V3 nt = ld3(nrm + 3 * t), nu = ld3(nrm + 3 * u);
   V3 d = ld3(cen + 3 * t) - ld3(cen + 3 * u);
@@ -335,6 +346,7 @@ struct AsmArgs {
   const int32_t* erow;
   const int32_t* trow;
   double skip_mag;           // skip far pairs with |e^{-jkR}| below this at the closest approach
+  double cut_r2;             // > 0: skip pairs whose squared centroid distance exceeds it
 };
 
 __device__ __forceinline__ void atomic_c(double* M, int64_t idx, Cx v) {
@@ -415,6 +427,7 @@ __global__ void __launch_bounds__(256) k_assemble_far(AsmArgs g) {
   const int u = g.t0 + bu * 16 + (threadIdx.x & 15);
   if (t >= g.t0 + n || u >= g.t0 + n || u < t) return;
   if (pair_is_near(g.cen, g.diam, t, u, c_rules.c_near)) return;
+  if (pair_beyond(g.cen, t, u, g.cut_r2)) return;
   if (g.skip_mag > 0.0) {
     V3 d = ld3(g.cen + 3 * t) - ld3(g.cen + 3 * u);
     double rmin = sqrt(dot(d, d)) - 0.5 * (g.diam[t] + g.diam[u]);
@@ -438,6 +451,7 @@ __global__ void __launch_bounds__(64) k_assemble_near(AsmArgs g, const int32_t* 
   if (p >= n_pairs) return;
   const int t = pairs[2 * p], u = pairs[2 * p + 1];
   if (!pair_is_near(g.cen, g.diam, t, u, c_rules.c_near)) return;
+  if (pair_beyond(g.cen, t, u, g.cut_r2)) return;
   Tri A = load_tri(g.xyz, g.tri, g.cen, g.nrm, g.area, t);
   Tri B = load_tri(g.xyz, g.tri, g.cen, g.nrm, g.area, u);
   Moments M;
@@ -462,6 +476,7 @@ void launch_assemble(const AsmLaunch& L, hipStream_t s) {
   g.ld_e = L.ld_e; g.ld_t = L.ld_t;
   g.erow = L.erow; g.trow = L.trow;
   g.skip_mag = L.skip_mag;
+  g.cut_r2 = L.cut_r2;
   const int n = L.t1 - L.t0;
   dim3 grid((n + 15) / 16, (n + 15) / 16);
   const bool wk = L.Kk != nullptr;

@@ -35,6 +35,7 @@ struct AsmLaunch {
   const int32_t* near_pairs = nullptr;   // candidate (t, u) pairs, t <= u
   int64_t n_near_pairs = 0;
   double skip_mag = 0.0;
+  double cut_r2 = 0.0;   // > 0: only pairs with squared centroid distance <= cut_r2 (sparse interior operators)
 };
 void launch_assemble(const AsmLaunch& L, hipStream_t s);
 

@@ -13,7 +13,8 @@
 // launch can run concurrently with the projection and the FFT.  In each phase a
 // block is split into P_i panels so that no panel exceeds a quarter of the
 // phase's ideal per-slot load (the moldable step), and the panels are ordered or
-// placed on their estimated time:
+// placed on their estimated time (with the sparse Z~ of the high-frequency form there
+// are no dense Z_i rows, and phase 1 is a sparse product instead):
 //   mode 0: LPT (Alg. 1) on a flop-count estimate of the kernel as written: rows
 //           rounded up to the eight-row wave sweep times the row length rounded up
 //           to the 256-column chunk, since lanes past the end of a short row idle
@@ -53,7 +54,7 @@ void pack_tiles(Ctx& c, int mode) {
     double total = 0.0;
     for (int i = 0; i < nb; ++i) total += c.blocks[i].n * double((c.blocks[i].n + 1) & ~1);
     const double ideal = total / S;
-    for (int i = 0; i < nb; ++i) {
+    for (int i = 0; i < nb && !(phase == 1 && c.hf_sparse); ++i) {   // sparse Z~: no dense rows of Z_i
       const int n = c.blocks[i].n, ld = (n + 1) & ~1, base = phase == 0 ? n : 0;
       int R;
       if (mode == 2) {
