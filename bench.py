@@ -59,6 +59,28 @@ def algorithmic_bytes(mesh, lay, mixed):
     return out
 
 
+def copy_bandwidth(gib=1.0, reps=20):
+    """Streaming copy bandwidth of the device (bytes read + written per second): a plain
+    device-to-device copy of `gib` GiB (four times the last-level cache; small enough to fit
+    beside the built operator), best of `reps` timed with events."""
+    import torch
+    n = int(gib * 2 ** 30) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    best = float("inf")
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1) * 1e-3)
+    del a, b
+    torch.cuda.empty_cache()
+    return 2.0 * 4 * n / best
+
+
 def host_cpu():
     """CPU model and logical cores available to this process (from /proc/cpuinfo)."""
     model = "unknown"
@@ -524,10 +546,11 @@ def main():
                     help="skip the GMRES time-to-1e-6 runs (mixed GMRES-IR vs FP64, plane-wave excitation)")
     ap.add_argument("--solve-max-iter", type=int, default=1000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--sched", type=int, default=4,
+    ap.add_argument("--sched", type=int, default=3,
                     help="scheduling mode of the timed products: 0 LPT on flop counts, 1 LPT on the trained cost "
-                         "model, 2 naive, 3 dynamic dispatch in flop-count order, 4 dynamic dispatch in the trained "
-                         "model's order (the learned modes need the schedule study, which trains the model)")
+                         "model, 2 naive, 3 dynamic dispatch in flop-count order (default: the order the launch "
+                         "shape is tuned in), 4 dynamic dispatch in the trained model's order (the learned modes "
+                         "need the schedule study, which trains the model)")
     ap.add_argument("--copy-probe", type=float, default=0.0,
                     help="only run a plain device copy of this many GiB (HBM counter calibration) and exit")
     ap.add_argument("--no-sched-study", action="store_true",
@@ -538,6 +561,11 @@ def main():
                     help="only run the layered-medium study and print its JSON")
     ap.add_argument("--no-srr", action="store_true",
                     help="skip the split-ring array (64 SRRs, 100 GHz, AIM 64^3) product rates")
+    ap.add_argument("--graph-only", action="store_true",
+                    help="time the graph path only, without the staged eager breakdown (for kernel traces whose "
+                         "per-kernel averages are the graph-path launches)")
+    ap.add_argument("--tune-cache", default=None,
+                    help="autotuning cache file of the main workload's build (read, and appended after tuning)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the product is built and applied on a single MI355X "
@@ -567,7 +595,10 @@ def main():
     ctx.set_mesh(mesh.verts, mesh.tris, mesh.obj, mesh.n_obj)
     t0 = time.time()
     # the conductor-block preconditioner is only built for the solve
-    lay = ctx.build(freq=freq, grid=grid, sched_mode=0, verbose=1, precond=0 if args.no_solve else 1)
+    # the launch shape is tuned under dynamic dispatch, the queue form of the timed products
+    # (modes 3 and 4); the schedule study re-packs the same tiles in every mode
+    lay = ctx.build(freq=freq, grid=grid, sched_mode=3, verbose=1, precond=0 if args.no_solve else 1,
+                    tune_cache=args.tune_cache)
     log("build: %.1f s, n_e %d n_t %d nnzA %d nnzP %d tiles %d slots %d" % (
         time.time() - t0, lay.n_e, lay.n_t, lay.nnz_near_A, lay.nnz_near_phi, lay.n_tiles, lay.slots))
     n = lay.n_sys
@@ -628,12 +659,17 @@ def main():
         rate[name] = args.steps / dt[name]
     dt_mixed, dt_fp64 = dt["mixed"], dt["fp64"]
     # per-stage breakdown: eager and sequential, HIP events on the launch stream
-    dt_pm, st_mixed = timed(slim.SLIM_MIXED, args.steps)
-    dt_pd, st_fp64 = timed(slim.SLIM_FP64, args.steps)
-    log("mixed %.3f ms/matvec (staged eager %.3f ms: %s)" % (1e3 * dt_mixed / args.steps, 1e3 * dt_pm / args.steps,
-                                                           ["%.3f" % s for s in st_mixed]))
-    log("fp64  %.3f ms/matvec (staged eager %.3f ms: %s)" % (1e3 * dt_fp64 / args.steps, 1e3 * dt_pd / args.steps,
-                                                           ["%.3f" % s for s in st_fp64]))
+    staged = not args.graph_only
+    if staged:
+        dt_pm, st_mixed = timed(slim.SLIM_MIXED, args.steps)
+        dt_pd, st_fp64 = timed(slim.SLIM_FP64, args.steps)
+        log("mixed %.3f ms/matvec (staged eager %.3f ms: %s)" % (1e3 * dt_mixed / args.steps, 1e3 * dt_pm / args.steps,
+                                                               ["%.3f" % s for s in st_mixed]))
+        log("fp64  %.3f ms/matvec (staged eager %.3f ms: %s)" % (1e3 * dt_fp64 / args.steps, 1e3 * dt_pd / args.steps,
+                                                               ["%.3f" % s for s in st_fp64]))
+    else:
+        log("mixed %.3f ms/matvec, fp64 %.3f ms/matvec (graph path only)" % (1e3 * dt_mixed / args.steps,
+                                                                           1e3 * dt_fp64 / args.steps))
     # accuracy of the mixed product against the FP64 product, per row block
     ne = lay.n_e
     ym, yd = y.cpu().numpy(), y64.cpu().numpy()
@@ -648,8 +684,23 @@ def main():
     # figure (both launches back to back, nothing concurrent) beside it.
     t_int = 0.5 * (graph_ms["mixed"]["phase_M"] + graph_ms["mixed"]["phase_Z"]) * 1e-3
     achieved = 0.5 * bytes_m["internal"] / t_int
-    achieved_eager = bytes_m["internal"] / (st_mixed[0] * 1e-3)
+    achieved_eager = bytes_m["internal"] / (st_mixed[0] * 1e-3) if staged else None
+    # each launch on its own: the rows of M_i run beside the small pulse path only; the
+    # rows of Z_i share HBM with the projection and FFT of j by design, so the window of
+    # that launch is also given with the bytes of all three (the FFT ends inside it)
+    gm = graph_ms["mixed"]
+    half = 0.5 * bytes_m["internal"]
+    launches = {
+        "rows_M": {"ms": gm["phase_M"], "workgroups": lay.slots,
+                   "frac": half / (gm["phase_M"] * 1e-3) / HBM_PEAK},
+        "rows_Z": {"ms": gm["phase_Z"], "workgroups": lay.slots_z,
+                   "frac": half / (gm["phase_Z"] * 1e-3) / HBM_PEAK,
+                   "window_frac_with_projection_and_fft":
+                       (half + bytes_m["fft"] + bytes_m["project"]) / (gm["phase_Z"] * 1e-3) / HBM_PEAK},
+    }
     traffic = internal_traffic(args.workload, lay)
+    copy_bw = copy_bandwidth()
+    log("streaming copy: %.3f TB/s" % (copy_bw / 1e12))
     result = {
         "metric": METRIC,
         "value": args.steps / dt_mixed,
@@ -672,14 +723,16 @@ def main():
             "sched_mode": args.sched,
         },
         "fp64": {"value": args.steps / dt_fp64, "unit": "matvecs/s", "ms_per_step": 1e3 * dt_fp64 / args.steps,
-                 "median_ms_per_step": step_ms["fp64"], "stage_ms": st_fp64,
+                 "median_ms_per_step": step_ms["fp64"], "stage_ms": st_fp64 if staged else None,
                  "graph_path_ms": graph_ms["fp64"]},
         "graph_path_ms_mixed": graph_ms["mixed"],
-        "tuned_shapes": {"slots": lay.slots, "fft_zblock": lay.fft_zblock, "rows_per_wave": lay.rows_per_wave},
+        "tuned_shapes": {"slots": lay.slots, "slots_z_rows": lay.slots_z, "fft_zblock": lay.fft_zblock,
+                         "rows_per_wave": lay.rows_per_wave},
         "stage_ms_mixed": {"internal": st_mixed[0], "project": st_mixed[1], "fft": st_mixed[2],
-                           "pulse_rows": st_mixed[3], "rwg_rows": st_mixed[4], "cont_rows": st_mixed[5]},
+                           "pulse_rows": st_mixed[3], "rwg_rows": st_mixed[4],
+                           "cont_rows": st_mixed[5]} if staged else None,
         "mixed_vs_fp64_rel_err": {"y1": err[0], "y2": err[1]},
-        "staged_eager_matvecs_per_s": {"mixed": args.steps / dt_pm, "fp64": args.steps / dt_pd},
+        "staged_eager_matvecs_per_s": {"mixed": args.steps / dt_pm, "fp64": args.steps / dt_pd} if staged else None,
         "algorithmic_bytes_mixed": bytes_m,
         "hbm_frac_whole_product": sum(bytes_m.values()) / (dt_mixed / args.steps) / HBM_PEAK,
         "roofline": {"kernel": "k_internal<mixed> (internal blocks; two launches per product), graph path",
@@ -687,7 +740,10 @@ def main():
                      "frac": achieved / HBM_PEAK, "traffic": traffic,
                      "algorithmic_bytes_per_launch": 0.5 * bytes_m["internal"],
                      "mean_launch_ms": 1e3 * t_int,
-                     "staged_eager": {"achieved": achieved_eager / 1e9, "frac": achieved_eager / HBM_PEAK}},
+                     "measured_copy_GBps": copy_bw / 1e9, "frac_of_measured_copy": achieved / copy_bw,
+                     "staged_eager": ({"achieved": achieved_eager / 1e9, "frac": achieved_eager / HBM_PEAK}
+                                      if staged else None),
+                     "launches": launches},
     }
     if schedule is not None:
         result["schedule"] = schedule

@@ -132,15 +132,19 @@ typedef struct {
      conductor-block preconditioner is not built in this mode (precond must be 0,
      else SLIM_E_UNSUPPORTED).                                                       */
   double hf_radius;
+  int32_t slots_z;        /* with slots > 0: persistent workgroups of the launch of the
+                             rows of Z_i (0 = slots); ignored when slots = 0 (tuned)  */
 } slim_build_opts;
 
 /* Fill `o` with the defaults used by the tests (near_cheb 3, n_far 4, n_near 5,
  * levels 3, q 0.25, n_r 5, n_t 6, c_near 2, LPT, autotuned slot count, plane
  * z block and rows per wave, graphs on, no tuning cache).
  * Autotuning (slots = 0) times the whole mixed product for 2, 4 and 8 persistent
- * internal workgroups per compute unit, times the "auto" kernel shapes, at build
- * time and keeps the fastest.  A tuning cache entry for the same shape skips the
- * timing.  With slots > 0 nothing is timed: auto shapes take 64 and 8.         */
+ * internal workgroups per compute unit, times the "auto" kernel shapes, times the
+ * workgroups of the launch of the rows of Z_i (as many, or one per compute unit),
+ * at build time and keeps the fastest.  A tuning cache entry for the same shape
+ * skips the timing.  With slots > 0 nothing is timed: auto shapes take 64 and 8,
+ * and both launches use `slots` workgroups.                                      */
 void slim_default_build_opts(slim_build_opts* o);
 
 typedef struct {
@@ -164,6 +168,9 @@ typedef struct {
   int32_t rows_per_wave;
   int64_t z_nnz;                       /* stored entries of the sparse Z~ (hf_radius > 0),
                                           0 with dense interior operators           */
+  int32_t slots_z;                     /* persistent workgroups of the launch of the rows of
+                                          Z_i (tuned with the slot count; it runs beside the
+                                          projection and FFT of j)                   */
 } slim_layout;
 
 typedef struct {
@@ -424,9 +431,19 @@ slim_status slim_sched_export(slim_ctx* ctx, double* out, int64_t* n);
  * these samples.  SLIM_E_ARG on non-finite samples. */
 slim_status slim_sched_train_data(slim_ctx* ctx, int64_t n, const double* samples, int32_t epochs, double lr,
                                   double* final_loss);
-/* 0 = LPT on flop counts, 1 = MLP-predicted times, 2 = naive (object order,
- * round robin); re-packs the work queues and re-captures the graphs. */
+/* 0 = LPT on flop counts, 1 = LPT on MLP-predicted times, 2 = naive (object
+ * order, round robin), 3 = dynamic dispatch in decreasing flop-count order, 4 =
+ * dynamic dispatch in decreasing predicted-time order (Sec. III-C scheduling on
+ * persistent workgroups); re-packs the work queues and re-captures the graphs.
+ * Modes 1 and 4 need a trained cost model (SLIM_E_STATE otherwise). */
 slim_status slim_sched_set_mode(slim_ctx* ctx, int32_t mode);
+/* Persistent workgroups of the two launches of the internal product: `slots` for
+ * the rows of M_i, `slots_z` for the rows of Z_i (0 = slots), as the build options
+ * of the same names; re-packs the queues in the current mode and re-captures the
+ * graphs (the build's autotuned shape is replaced).  Results do not depend on the
+ * shape.  SLIM_E_ARG outside [1, 65536] (slots_z: [0, 65536]); SLIM_E_STATE before
+ * slim_build. */
+slim_status slim_sched_set_shape(slim_ctx* ctx, int32_t slots, int32_t slots_z);
 
 /* --- cost-model network kernels (exposed for gradient checks) -------------- */
 /* FP32 MLP F -> 64 -> 64 -> 1 (tanh).  params (device, fp32) in the order

@@ -435,16 +435,19 @@ static void build_plain_external(Ctx& c, hipStream_t s) {
 // kept in an optional text cache keyed by (kernel, shape, architecture).
 namespace {
 
-std::string tune_key(const Ctx& c, const char* arch, int cus) {
+// the shape is tuned for the queue form it will run with (static queues and dynamic
+// dispatch favour different workgroup counts)
+std::string tune_key(const Ctx& c, const char* arch, int cus, bool dynamic) {
   char buf[512];
-  std::snprintf(buf, sizeof(buf), "product|%s|cus=%d|n_e=%lld|n_t=%lld|n_obj=%d|grid=%dx%dx%d|entries=%lld|nnz=%lld+%lld",
+  std::snprintf(buf, sizeof(buf),
+                "product|%s|cus=%d|n_e=%lld|n_t=%lld|n_obj=%d|grid=%dx%dx%d|entries=%lld|nnz=%lld+%lld|queues=%s",
                 arch, cus, (long long)c.rwg.n_e, (long long)c.rwg.n_t, c.rwg.n_obj, c.plain ? 0 : c.grid.N[0],
                 c.plain ? 0 : c.grid.N[1], c.plain ? 0 : c.grid.N[2], (long long)c.arena_elems, (long long)c.nnz_A,
-                (long long)c.nnz_P);
+                (long long)c.nnz_P, dynamic ? "dynamic" : "static");
   return buf;
 }
 
-bool tune_cache_lookup(const char* path, const std::string& key, int& per_cu, int& zb, int& rw) {
+bool tune_cache_lookup(const char* path, const std::string& key, int& per_cu, int& zb, int& rw, int& zpc) {
   if (!path) return false;
   FILE* f = std::fopen(path, "r");
   if (!f) return false;
@@ -454,10 +457,11 @@ bool tune_cache_lookup(const char* path, const std::string& key, int& per_cu, in
     std::string l(line);
     const size_t bar = l.rfind("|per_cu=");
     if (bar == std::string::npos || l.compare(0, bar, key) != 0 || bar != key.size()) continue;
-    int a = 0, b = 0, r = 0;
-    if (std::sscanf(l.c_str() + bar, "|per_cu=%d|zblock=%d|rw=%d", &a, &b, &r) == 3 && a > 0 && (b == 1 || b == 8) &&
-        (r == 4 || r == 8)) {
+    int a = 0, b = 0, r = 0, z = 0;
+    const int got = std::sscanf(l.c_str() + bar, "|per_cu=%d|zblock=%d|rw=%d|z_per_cu=%d", &a, &b, &r, &z);
+    if (got >= 3 && a > 0 && (b == 1 || b == 8) && (r == 4 || r == 8)) {
       per_cu = a; zb = b; rw = r;
+      zpc = got == 4 && z > 0 && z <= a ? z : a;   // older lines: the rows of Z_i on every slot
       found = true;   // the last matching line wins
     }
   }
@@ -465,11 +469,11 @@ bool tune_cache_lookup(const char* path, const std::string& key, int& per_cu, in
   return found;
 }
 
-void tune_cache_store(const char* path, const std::string& key, int per_cu, int zb, int rw, double ms) {
+void tune_cache_store(const char* path, const std::string& key, int per_cu, int zb, int rw, int zpc, double ms) {
   if (!path) return;
   FILE* f = std::fopen(path, "a");
   if (!f) return;   // an unwritable cache only costs the timing next time
-  std::fprintf(f, "%s|per_cu=%d|zblock=%d|rw=%d|ms=%.4f\n", key.c_str(), per_cu, zb, rw, ms);
+  std::fprintf(f, "%s|per_cu=%d|zblock=%d|rw=%d|z_per_cu=%d|ms=%.4f\n", key.c_str(), per_cu, zb, rw, zpc, ms);
   std::fclose(f);
 }
 
@@ -486,14 +490,17 @@ static void autotune(Ctx& c, const slim_build_opts& o, hipStream_t s) {
   }
   // before any training the learned modes pack on flop counts
   const int pack_mode = o.sched_mode == 1 ? 0 : o.sched_mode == 4 ? 3 : o.sched_mode;
-  const std::string key = tune_key(c, arch, cus);
-  int per_cu = 0, zb = 0, rw = 0;
-  if (tune_cache_lookup(o.tune_cache, key, per_cu, zb, rw)) {
+  const std::string key = tune_key(c, arch, cus, pack_mode == 3);
+  int per_cu = 0, zb = 0, rw = 0, zpc = 0;
+  if (tune_cache_lookup(o.tune_cache, key, per_cu, zb, rw, zpc)) {
     c.slots = per_cu * cus;
+    c.slots_z = zpc * cus;
     c.fft_zsh = zb == 8 ? 3 : 0;
     c.rw_mixed = rw;
     pack_tiles(c, pack_mode);
-    if (o.verbose) std::fprintf(stderr, "[slim build] autotune: cached %d per CU, z block %d, rw %d\n", per_cu, zb, rw);
+    if (o.verbose)
+      std::fprintf(stderr, "[slim build] autotune: cached %d per CU (rows of Z_i: %d), z block %d, rw %d\n", per_cu, zpc,
+                   zb, rw);
     return;
   }
   SLIM_HIP(hipMemsetAsync(c.d_x64.p, 0, c.d_x64.bytes, s));
@@ -501,15 +508,20 @@ static void autotune(Ctx& c, const slim_build_opts& o, hipStream_t s) {
   std::vector<int> zbs = o.fft_zblock > 0 || c.plain ? std::vector<int>{1 << c.fft_zsh} : std::vector<int>{1, 8};
   std::vector<int> rws = o.rows_per_wave > 0 ? std::vector<int>{c.rw_mixed} : std::vector<int>{4, 8};
   const int per_cu_set[3] = {2, 4, 8};
-  struct Cand { int per_cu, zb, rw; double ms; };
+  // workgroups of the launch of the rows of Z_i, which runs beside the projection and FFT
+  // of j: as many as the other launch, or one per CU (room for the FFT's workgroups)
+  struct Cand { int per_cu, zb, rw, zpc; double ms; };
   std::vector<Cand> cand;
   for (int pc : per_cu_set)
     for (int z : zbs)
-      for (int r : rws) cand.push_back({pc, z, r, 1e300});
+      for (int r : rws)
+        for (int zpc : {pc, 1})
+          if (zpc == pc || !c.plain) cand.push_back({pc, z, r, zpc, 1e300});
   for (int round = 0; round < 2; ++round)
     for (Cand& k : cand) {
-      if (k.per_cu * cus != c.slots) {
+      if (k.per_cu * cus != c.slots || k.zpc * cus != c.zslots()) {
         c.slots = k.per_cu * cus;
+        c.slots_z = k.zpc * cus;
         pack_tiles(c, pack_mode);
       }
       c.fft_zsh = k.zb == 8 ? 3 : 0;
@@ -519,15 +531,16 @@ static void autotune(Ctx& c, const slim_build_opts& o, hipStream_t s) {
   const Cand* best = &cand[0];
   for (const Cand& k : cand) {
     if (o.verbose)
-      std::fprintf(stderr, "[slim build] autotune: %d per CU, z block %d, rw %d -> %.3f ms per product\n", k.per_cu,
-                   k.zb, k.rw, k.ms);
+      std::fprintf(stderr, "[slim build] autotune: %d per CU (rows of Z_i: %d), z block %d, rw %d -> %.3f ms per product\n",
+                   k.per_cu, k.zpc, k.zb, k.rw, k.ms);
     if (k.ms < best->ms) best = &k;
   }
   c.slots = best->per_cu * cus;
+  c.slots_z = best->zpc * cus;
   c.fft_zsh = best->zb == 8 ? 3 : 0;
   c.rw_mixed = best->rw;
   pack_tiles(c, pack_mode);
-  tune_cache_store(o.tune_cache, key, best->per_cu, best->zb, best->rw, best->ms);
+  tune_cache_store(o.tune_cache, key, best->per_cu, best->zb, best->rw, best->zpc, best->ms);
 }
 
 void build_all(Ctx& c, const slim_build_opts& o) {
@@ -641,8 +654,10 @@ void build_all(Ctx& c, const slim_build_opts& o) {
                "rows_per_wave must be 0, 4 or 8");
   c.fft_zsh = o.fft_zblock == 1 ? 0 : 3;
   c.rw_mixed = o.rows_per_wave > 0 ? o.rows_per_wave : 8;
+  SLIM_REQUIRE(o.slots_z >= 0, SLIM_E_ARG, "slots_z must be >= 0");
   if (o.slots > 0) {
     c.slots = o.slots;
+    c.slots_z = o.slots_z;
     pack_tiles(c, o.sched_mode);
   } else {
     autotune(c, o, s);
@@ -675,6 +690,7 @@ void build_all(Ctx& c, const slim_build_opts& o) {
   Lo.fft_zblock = c.plain ? 0 : 1 << c.fft_zsh;
   Lo.rows_per_wave = c.rw_mixed;
   Lo.z_nnz = c.z_nnz;
+  Lo.slots_z = c.zslots();
   c.built = true;
 }
 

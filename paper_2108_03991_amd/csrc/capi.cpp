@@ -61,6 +61,7 @@ void slim_default_build_opts(slim_build_opts* o) {
   o->rows_per_wave = 0;
   o->tune_cache = nullptr;
   o->hf_radius = 0.0;
+  o->slots_z = 0;
 }
 
 slim_status slim_create(int32_t hip_device, slim_ctx** out) {
@@ -561,6 +562,22 @@ slim_status slim_sched_set_mode(slim_ctx* h, int32_t mode) {
     pack_tiles(h->c, mode);
     h->c.last_stamps.clear();
     h->c.layout.n_tiles = int64_t(h->c.tiles.size());
+    return SLIM_OK;
+  });
+}
+
+slim_status slim_sched_set_shape(slim_ctx* h, int32_t slots, int32_t slots_z) {
+  return guard(h, [&]() {
+    SLIM_REQUIRE(h->c.built, SLIM_E_STATE, "operator not built");
+    SLIM_REQUIRE(slots > 0 && slots <= (1 << 16), SLIM_E_ARG, "slots must be in [1, 65536]");
+    SLIM_REQUIRE(slots_z >= 0 && slots_z <= (1 << 16), SLIM_E_ARG, "slots_z must be in [0, 65536]");
+    h->c.slots = slots;
+    h->c.slots_z = slots_z;
+    pack_tiles(h->c, h->c.sched_mode);
+    h->c.last_stamps.clear();
+    h->c.layout.n_tiles = int64_t(h->c.tiles.size());
+    h->c.layout.slots = h->c.slots;
+    h->c.layout.slots_z = h->c.zslots();
     return SLIM_OK;
   });
 }

@@ -70,18 +70,27 @@ struct Ctx {
   // ---- work queues of the persistent internal kernel ----
   std::vector<Tile> tiles;              // grouped by slot
   std::vector<int32_t> slot_start;      // slots+1
-  DevBuf d_tiles, d_slot_start;         // slot_start: 2 x (slots + 1), one range table per phase
+  DevBuf d_tiles, d_slot_start;         // slot_start: (slots + 1) + (zslots + 1), one range table per phase
   int32_t phase_first[2] = {0, 0};      // tiles of phase 0 (rows of M_i) and phase 1 (rows of Z_i)
   int32_t phase_count[2] = {0, 0};
   bool dynamic = false;                 // dynamic dispatch (scheduling modes 3 and 4)
-  DevBuf d_qctr;                        // dispatch counters: GEMV phases 0, 1; block product phases 0, 1
+  DevBuf d_qctr;                        // dispatch counters: GEMV phases 0, 1; block product phases 0, 1;
+                                        // FP64 GEMV phase 1 (its own grid)
   int slots = 0;
+  int slots_z = 0;                      // workgroups of the launch of the rows of Z_i (0: slots)
+  int zslots() const { return slots_z > 0 ? slots_z : slots; }
+  // workgroups of the launch of the rows of Z_i in one precision: slots_z is chosen for
+  // the mixed path, whose launch runs beside the FFT; the FP64 launch is bound by its
+  // arithmetic and latency and takes the M rows' count wherever the queue allows it
+  // (dynamic dispatch draws from one list, so any grid serves it)
+  int zgrid(bool f64) const { return f64 && dynamic ? std::max(slots, zslots()) : zslots(); }
   int tile_rows = 64;
   int rw_mixed = 8;                     // rows per wave of the mixed internal kernel (4 or 8)
   int sched_mode = 0;
   bool record = false;
   DevBuf d_stamps;                      // 2 x n_tiles uint64 timestamps
-  DevBuf d_span;                        // 2 phases x 2 x slots uint64: start and end of every workgroup (graph-path timing)
+  DevBuf d_span;                        // 2 x (slots + zslots) uint64: start and end of every workgroup of both
+                                        // launches (graph-path timing)
   std::vector<double> last_stamps;
 
   // ---- I_x (sparse: the other edges of T+ and T-), per RWG row ----

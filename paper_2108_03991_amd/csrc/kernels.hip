@@ -174,16 +174,21 @@ __device__ __forceinline__ float4 ntload(const float2* p) {
 // list position t mod (count + gridDim.x).  Launches on one counter must not overlap.
 struct TileQueue {
   const int4* tiles;
-  const int32_t* start;        // static: slot ranges (absolute tile indices)
+  const int32_t* start;        // static: slot ranges (absolute tile indices) of nslots slots
   unsigned long long* ctr;     // dynamic: ticket counter (null: static)
   int32_t first, count;
+  int32_t nslots;              // static: workgroups at or past nslots have no queue
 };
+
+__device__ __forceinline__ int queue_begin(const TileQueue& q) {
+  return (q.ctr || int(blockIdx.x) >= q.nslots) ? 0 : q.start[blockIdx.x];
+}
 
 // Index of the workgroup's next tile, or -1 when it has none.  Every thread of the
 // workgroup calls it (the dynamic form has barriers); `it` starts at
-// q.start[blockIdx.x] and s_next is a workgroup-shared int.
+// queue_begin(q) and s_next is a workgroup-shared int.
 __device__ __forceinline__ int next_tile(const TileQueue& q, int& it, int* s_next) {
-  if (!q.ctr) return it < q.start[blockIdx.x + 1] ? it++ : -1;
+  if (!q.ctr) return (int(blockIdx.x) < q.nslots && it < q.start[blockIdx.x + 1]) ? it++ : -1;
   if (threadIdx.x == 0) {
     const unsigned long long T = (unsigned long long)(q.count) + gridDim.x;
     const unsigned long long t = atomicAdd(q.ctr, 1ull) % T;
@@ -212,7 +217,7 @@ __global__ void __launch_bounds__(256) k_internal(const float2* __restrict__ hi,
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   if (span && threadIdx.x == 0) span[2 * slot] = wall_clock64();
   __shared__ int s_next;
-  int it = q.ctr ? 0 : q.start[slot];
+  int it = queue_begin(q);
   for (int ti = next_tile(q, it, &s_next); ti >= 0; ti = next_tile(q, it, &s_next)) {
     const int4 tl = q.tiles[ti];      // block, row0, rows, slot
     unsigned long long t_start = 0;
@@ -355,12 +360,14 @@ __global__ void k_split_h(const double2* X, int64_t nsys, int64_t ne, int R, int
   Hs[3 * plane + o] = __bf16(im - float(ih));
 }
 
-// One wave computes RG 16-row groups x NCG 16-column groups.  The next K chunk's A
-// fragments (HBM) are loaded while the current chunk's MFMAs run; the H fragments of a
-// column group (L2-resident, one contiguous kilobyte per load) are read just before
-// their products, so that few registers are held across the loop and several waves fit
-// a SIMD.  Within a column group the 12 products are issued term by term over the four
-// accumulators, so that dependent MFMAs are four apart.
+// A workgroup sweeps 64 rows of a tile at a time, one 16-row group per wave, times NCG
+// 16-column groups.  The four waves share each K chunk of H: its split fragments
+// (4 planes x 16 NCG columns x 32 slots, contiguous in every plane) are loaded by the
+// whole workgroup, one 16-byte piece per thread and column group, into one of two LDS
+// buffers while the previous chunk's MFMAs run, with one barrier per chunk.  Each wave
+// loads the next chunk's A fragments (HBM) the same way.  Within a column group the 12
+// products are issued term by term over the four accumulators.  Every wave runs the
+// same number of sweeps (rows past the tile masked), so the barriers are uniform.
 template <int NCG, int RG>
 __global__ void __launch_bounds__(256) k_internal_mfma(const float2* __restrict__ hi, const BlockDev* __restrict__ blocks,
                                                        const TileQueue q0, const TileQueue q1,
@@ -368,106 +375,120 @@ __global__ void __launch_bounds__(256) k_internal_mfma(const float2* __restrict_
                                                        int64_t plane, int ldc, int col0,
                                                        const float2* __restrict__ H64, int64_t ne, int ncol,
                                                        float2* __restrict__ E, float2* __restrict__ J) {
+  static_assert(RG == 1, "one 16-row group per wave");
+  constexpr int PIECES = 64 * NCG;        // 16-byte pieces of one plane's chunk (16 NCG columns x 32 slots)
+  __shared__ bf16x8 hbuf[2][4 * PIECES];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int lr = lane & 15, lg = lane >> 4;
   __shared__ int s_next;
   // the two phases' lists (rows of M_i, then rows of Z_i), one after the other
   for (int phase = 0; phase < 2; ++phase) {
    const TileQueue& q = phase == 0 ? q0 : q1;
-   int it = q.ctr ? 0 : q.start[blockIdx.x];
+   int it = queue_begin(q);
    for (int ti = next_tile(q, it, &s_next); ti >= 0; ti = next_tile(q, it, &s_next)) {
     const int4 tl = q.tiles[ti];
     const BlockDev B = blocks[tl.x];
     const int n = B.n, ld = (n + 1) & ~1, rend = tl.y + tl.z;
     const int64_t h0 = hoff[tl.x];
-    for (int r0 = tl.y + 16 * RG * wave; r0 < rend; r0 += 64 * RG) {
-      f32x4 acc[RG][NCG][4];
+    // the workgroup's pieces of a chunk: piece p = threadIdx.x + 256 j -> plane p / PIECES
+    auto load_h = [&](int k0, bf16x8* hs) {
+      const int64_t cb = (((h0 + k0) >> 5) * ldc + col0) * 32;
 #pragma unroll
-      for (int r = 0; r < RG; ++r)
+      for (int j = 0; j < NCG; ++j) {
+        const int p = threadIdx.x + 256 * j, pl = p / PIECES, w = p % PIECES;
+        hs[j] = *reinterpret_cast<const bf16x8*>(Hs + pl * plane + cb + 8 * w);
+      }
+    };
+    auto store_h = [&](int buf, const bf16x8* hs) {
 #pragma unroll
-        for (int g = 0; g < NCG; ++g)
+      for (int j = 0; j < NCG; ++j) hbuf[buf][threadIdx.x + 256 * j] = hs[j];
+    };
+    for (int r0s = tl.y; r0s < rend; r0s += 64) {
+      const int r0 = r0s + 16 * wave;
+      f32x4 acc[NCG][4];
 #pragma unroll
-          for (int q = 0; q < 4; ++q) acc[r][g][q] = f32x4{0.f, 0.f, 0.f, 0.f};
-      // A fragments of the K chunk at k0: 8 complex (4 pairs) per row group, zero past the tile or row
-      auto load_a = [&](int k0, float4 (*a)[4]) {
+      for (int g = 0; g < NCG; ++g)
 #pragma unroll
-        for (int r = 0; r < RG; ++r) {
-          const int row = r0 + 16 * r + lr;
-          const float2* arow = hi + B.off + int64_t(row) * ld;
+        for (int q = 0; q < 4; ++q) acc[g][q] = f32x4{0.f, 0.f, 0.f, 0.f};
+      const int row = r0 + lr;
+      const float2* arow = hi + (B.off + int64_t(row) * ld);
+      // A fragment of the K chunk at k0: 8 complex (4 pairs), zero past the tile or row
+      auto load_a = [&](int k0, float4* a) {
 #pragma unroll
-          for (int p = 0; p < 4; ++p) {
-            const int kk = k0 + 8 * p + 2 * lg;
-            a[r][p] = (row < rend && kk < ld) ? ntload(arow + kk) : make_float4(0.f, 0.f, 0.f, 0.f);
-          }
+        for (int p = 0; p < 4; ++p) {
+          const int kk = k0 + 8 * p + 2 * lg;
+          a[p] = (row < rend && kk < ld) ? ntload(arow + kk) : make_float4(0.f, 0.f, 0.f, 0.f);
         }
       };
-      float4 a_cur[RG][4], a_nxt[RG][4];
+      float4 a_cur[4], a_nxt[4];
+      bf16x8 hs[NCG];
+      load_h(0, hs);
       load_a(0, a_cur);
+      store_h(0, hs);
+      __syncthreads();
+      int buf = 0;
       for (int k0 = 0; k0 < n; k0 += 32) {
         const bool more = k0 + 32 < n;
-        if (more) load_a(k0 + 32, a_nxt);
-        bf16x8 ah[RG][2], al[RG][2];   // [r][0]: real part, [r][1]: imaginary part
-#pragma unroll
-        for (int r = 0; r < RG; ++r) {
+        if (more) {
+          load_a(k0 + 32, a_nxt);
+          load_h(k0 + 32, hs);
+        }
+        bf16x8 ah[2], al[2];   // [0]: real part, [1]: imaginary part
+        {
           float re[8], im[8];
 #pragma unroll
           for (int p = 0; p < 4; ++p) {
-            re[2 * p] = a_cur[r][p].x; im[2 * p] = a_cur[r][p].y;
-            re[2 * p + 1] = a_cur[r][p].z; im[2 * p + 1] = a_cur[r][p].w;
+            re[2 * p] = a_cur[p].x; im[2 * p] = a_cur[p].y;
+            re[2 * p + 1] = a_cur[p].z; im[2 * p + 1] = a_cur[p].w;
           }
-          split_bf16(re, ah[r][0], al[r][0]);
-          split_bf16(im, ah[r][1], al[r][1]);
+          split_bf16(re, ah[0], al[0]);
+          split_bf16(im, ah[1], al[1]);
         }
-        const int64_t cb = ((h0 + k0) >> 5) * ldc + col0;     // chunk of K, first column
         // accumulators: 0 = Ar Hr, 1 = Ai Hi, 2 = Ar Hi, 3 = Ai Hr; planes: 0 Hr hi, 1 Hr lo, 2 Hi hi, 3 Hi lo
         // term 0: a_hi b_hi, term 1: a_hi b_lo, term 2: a_lo b_hi
 #pragma unroll
         for (int g = 0; g < NCG; ++g) {
           bf16x8 hv[4];
-          const int64_t o = (cb + 16 * g + lr) * 32 + 8 * lg;
 #pragma unroll
-          for (int pl = 0; pl < 4; ++pl) hv[pl] = *reinterpret_cast<const bf16x8*>(Hs + pl * plane + o);
+          for (int pl = 0; pl < 4; ++pl) hv[pl] = hbuf[buf][pl * PIECES + (16 * g + lr) * 4 + lg];
 #pragma unroll
           for (int term = 0; term < 3; ++term)
 #pragma unroll
-            for (int r = 0; r < RG; ++r)
-#pragma unroll
-              for (int q = 0; q < 4; ++q) {
-                const int ai = (q == 0 || q == 2) ? 0 : 1;     // Ar for accumulators 0, 2; Ai for 1, 3
-                const int bp = (q == 0 || q == 3) ? 0 : 2;     // Hr for accumulators 0, 3; Hi for 1, 2
-                const bf16x8 av = term == 2 ? al[r][ai] : ah[r][ai];
-                const bf16x8 bv = term == 1 ? hv[bp + 1] : hv[bp];
-                acc[r][g][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[r][g][q], 0, 0, 0);
-              }
+            for (int q = 0; q < 4; ++q) {
+              const int ai = (q == 0 || q == 2) ? 0 : 1;     // Ar for accumulators 0, 2; Ai for 1, 3
+              const int bp = (q == 0 || q == 3) ? 0 : 2;     // Hr for accumulators 0, 3; Hi for 1, 2
+              const bf16x8 av = term == 2 ? al[ai] : ah[ai];
+              const bf16x8 bv = term == 1 ? hv[bp + 1] : hv[bp];
+              acc[g][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[g][q], 0, 0, 0);
+            }
         }
         if (more) {
+          store_h(buf ^ 1, hs);
 #pragma unroll
-          for (int r = 0; r < RG; ++r)
-#pragma unroll
-            for (int p = 0; p < 4; ++p) a_cur[r][p] = a_nxt[r][p];
+          for (int p = 0; p < 4; ++p) a_cur[p] = a_nxt[p];
         }
+        __syncthreads();   // the next chunk is in LDS; this one may be overwritten
+        buf ^= 1;
       }
       // epilogue: e rows (row < n) and j = H - g rows (row >= n), column 16 g + lr
 #pragma unroll
-      for (int r = 0; r < RG; ++r)
+      for (int g = 0; g < NCG; ++g) {
+        const int col = 16 * g + lr;
+        if (col >= ncol) continue;
 #pragma unroll
-        for (int g = 0; g < NCG; ++g) {
-          const int col = 16 * g + lr;
-          if (col >= ncol) continue;
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            const int rr = r0 + 16 * r + 4 * lg + q;
-            if (rr >= rend) continue;
-            const float yr = acc[r][g][0][q] - acc[r][g][1][q], yi = acc[r][g][2][q] + acc[r][g][3][q];
-            if (rr < n) {
-              E[int64_t(col) * ne + B.e0 + rr] = make_float2(yr, yi);
-            } else {
-              const int64_t k = int64_t(col) * ne + B.e0 + (rr - n);
-              const float2 h = H64[k];
-              J[k] = make_float2(h.x - yr, h.y - yi);
-            }
+        for (int q = 0; q < 4; ++q) {
+          const int rr = r0 + 4 * lg + q;
+          if (rr >= rend) continue;
+          const float yr = acc[g][0][q] - acc[g][1][q], yi = acc[g][2][q] + acc[g][3][q];
+          if (rr < n) {
+            E[int64_t(col) * ne + B.e0 + rr] = make_float2(yr, yi);
+          } else {
+            const int64_t k = int64_t(col) * ne + B.e0 + (rr - n);
+            const float2 h = H64[k];
+            J[k] = make_float2(h.x - yr, h.y - yi);
           }
         }
+      }
     }
    }
   }
@@ -532,45 +553,62 @@ __global__ void __launch_bounds__(256) k_project(const int32_t* pe_node, const i
 }
 
 // ---------------------------------------------------------------------------
-// A5 + A6 for pulses: phi_t = W_rho Phi_rho + L_phi,NR (B c0rho); one wave per row.
-// ---------------------------------------------------------------------------
+// Sum over the LPR lanes of a row group (LPR a power of two up to 64).
+template <int LPR, bool F64>
+__device__ __forceinline__ typename P<F64>::T row_sum(typename P<F64>::T v) {
+#pragma unroll
+  for (int off = LPR / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, LPR);
+  return v;
+}
+
+// A5 + A6 for pulses: phi_t = W_rho Phi_rho + L_phi,NR (B c0rho); sixteen lanes per row
+// (four rows per wave), two entries per lane per trip.
 template <bool F64>
 __global__ void __launch_bounds__(256) k_phi(const int32_t* wt_base, const void* wt_w, const void* octv, int64_t N3,
                                              int Nx, int NxNy, const int64_t* ptr, const int32_t* col,
                                              const void* valv, const void* rhov, void* phiv, int64_t n_t) {
   using T = typename P<F64>::T;
-  const int64_t t = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  if (t >= n_t) return;
-  const T* w = reinterpret_cast<const T*>(wt_w);
-  const C2<T>* Phi = reinterpret_cast<const C2<T>*>(octv) + 3 * N3;
-  const C2<T>* val = reinterpret_cast<const C2<T>*>(valv);
-  const C2<T>* rho = reinterpret_cast<const C2<T>*>(rhov);
+  constexpr int LPR = 16;
+  const int64_t t = (int64_t(blockIdx.x) * 256 + threadIdx.x) / LPR;
+  const int lane = threadIdx.x & (LPR - 1);
+  const bool live = t < n_t;      // every lane stays for the shuffles
   T sr = 0, si = 0;
-  if (lane < 27) {
-    const int64_t node = wt_base[t] + (lane % 3) + Nx * ((lane / 3) % 3) + int64_t(NxNy) * (lane / 9);
-    const T wv = w[27 * t + lane];
-    sr = wv * Phi[node].x;
-    si = wv * Phi[node].y;
+  if (live) {
+    const T* w = reinterpret_cast<const T*>(wt_w);
+    const C2<T>* Phi = reinterpret_cast<const C2<T>*>(octv) + 3 * N3;
+    const C2<T>* val = reinterpret_cast<const C2<T>*>(valv);
+    const C2<T>* rho = reinterpret_cast<const C2<T>*>(rhov);
+    const int64_t base = wt_base[t];
+#pragma unroll
+    for (int k = lane; k < 27; k += LPR) {
+      const int64_t node = base + (k % 3) + Nx * ((k / 3) % 3) + int64_t(NxNy) * (k / 9);
+      const T wv = w[27 * t + k];
+      sr += wv * Phi[node].x;
+      si += wv * Phi[node].y;
+    }
+    const int64_t zend = ptr[t + 1];
+    for (int64_t z = ptr[t] + lane; z < zend; z += 2 * LPR) {
+      const bool two = z + LPR < zend;
+      const int c0 = col[z], c1 = two ? col[z + LPR] : c0;
+      const C2<T> a0 = val[z], a1 = two ? val[z + LPR] : C2<T>{T(0), T(0)};
+      const C2<T> b0 = rho[c0], b1 = rho[c1];
+      sr += a0.x * b0.x - a0.y * b0.y + a1.x * b1.x - a1.y * b1.y;
+      si += a0.x * b0.y + a0.y * b0.x + a1.x * b1.y + a1.y * b1.x;
+    }
   }
-  const int64_t zend = ptr[t + 1];
-  for (int64_t z = ptr[t] + lane; z < zend; z += 128) {
-    const bool two = z + 64 < zend;
-    const int c0 = col[z], c1 = two ? col[z + 64] : c0;
-    const C2<T> a0 = val[z], a1 = two ? val[z + 64] : C2<T>{T(0), T(0)};
-    const C2<T> b0 = rho[c0], b1 = rho[c1];
-    sr += a0.x * b0.x - a0.y * b0.y + a1.x * b1.x - a1.y * b1.y;
-    si += a0.x * b0.y + a0.y * b0.x + a1.x * b1.y + a1.y * b1.x;
-  }
-  sr = wave_sum(sr);
-  si = wave_sum(si);
-  if (lane == 0) reinterpret_cast<C2<T>*>(phiv)[t] = {sr, si};
+  sr = row_sum<LPR, F64>(sr);
+  si = row_sum<LPR, F64>(si);
+  if (live && lane == 0) reinterpret_cast<C2<T>*>(phiv)[t] = {sr, si};
 }
 
 // ---------------------------------------------------------------------------
 // A5 + A6 + A7 for RWG rows: a = W_A Phi + L_A,NR j;
 // y1 = j k0 a + l (phi[T+] - phi[T-]) + I_x e / eta0  (written as complex128).
 // ---------------------------------------------------------------------------
+// Sixteen lanes per RWG row (four rows per wave): the 27-node W gather takes two
+// passes, the near-field row (about 265 entries at the 2000-conductor workload) is
+// strided two entries per lane per trip, and the row tail (phi of T+-, the I_x
+// entries) runs on the first lane of each row group, four rows at a time per wave.
 template <bool F64, bool AIM>
 __global__ void __launch_bounds__(256) k_rows_A(const int32_t* we_base, const void* we_w, const void* octv, int64_t N3,
                                                 int Nx, int NxNy, const int64_t* ptr, const int32_t* col,
@@ -580,42 +618,47 @@ __global__ void __launch_bounds__(256) k_rows_A(const int32_t* we_base, const vo
                                                 const double* ix_val, double k0, double inv_eta0, void* av,
                                                 double2* y, int64_t n_e) {
   using T = typename P<F64>::T;
-  const int64_t m = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  if (m >= n_e) return;
+  constexpr int LPR = 16;
+  const int64_t m = (int64_t(blockIdx.x) * 256 + threadIdx.x) / LPR;
+  const int lane = threadIdx.x & (LPR - 1);
+  const bool live = m < n_e;      // every lane stays for the shuffles
   T sr = 0, si = 0;
   if (AIM) {
-    const T* w = reinterpret_cast<const T*>(we_w) + 81 * m;
-    const C2<T>* Phi = reinterpret_cast<const C2<T>*>(octv);
-    if (lane < 27) {
-      const int64_t node = we_base[m] + (lane % 3) + Nx * ((lane / 3) % 3) + int64_t(NxNy) * (lane / 9);
+    if (live) {
+      const T* w = reinterpret_cast<const T*>(we_w) + 81 * m;
+      const C2<T>* Phi = reinterpret_cast<const C2<T>*>(octv);
+      const int64_t base = we_base[m];
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const C2<T> p = Phi[c * N3 + node];
-        sr += w[c * 27 + lane] * p.x;
-        si += w[c * 27 + lane] * p.y;
+      for (int k = lane; k < 27; k += LPR) {
+        const int64_t node = base + (k % 3) + Nx * ((k / 3) % 3) + int64_t(NxNy) * (k / 9);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const C2<T> p = Phi[c * N3 + node];
+          sr += w[c * 27 + k] * p.x;
+          si += w[c * 27 + k] * p.y;
+        }
+      }
+      const C2<T>* val = reinterpret_cast<const C2<T>*>(valv);
+      const C2<T>* j = reinterpret_cast<const C2<T>*>(jv);
+      // two entries per lane per trip: both column loads, then both gathers, are in flight together
+      const int64_t zend = ptr[m + 1];
+      for (int64_t z = ptr[m] + lane; z < zend; z += 2 * LPR) {
+        const bool two = z + LPR < zend;
+        const int c0 = col[z], c1 = two ? col[z + LPR] : c0;
+        const C2<T> a0 = val[z], a1 = two ? val[z + LPR] : C2<T>{T(0), T(0)};
+        const C2<T> b0 = j[c0], b1 = j[c1];
+        sr += a0.x * b0.x - a0.y * b0.y + a1.x * b1.x - a1.y * b1.y;
+        si += a0.x * b0.y + a0.y * b0.x + a1.x * b1.y + a1.y * b1.x;
       }
     }
-    const C2<T>* val = reinterpret_cast<const C2<T>*>(valv);
-    const C2<T>* j = reinterpret_cast<const C2<T>*>(jv);
-    // two entries per lane per trip: both column loads, then both gathers, are in flight together
-    const int64_t zend = ptr[m + 1];
-    for (int64_t z = ptr[m] + lane; z < zend; z += 128) {
-      const bool two = z + 64 < zend;
-      const int c0 = col[z], c1 = two ? col[z + 64] : c0;
-      const C2<T> a0 = val[z], a1 = two ? val[z + 64] : C2<T>{T(0), T(0)};
-      const C2<T> b0 = j[c0], b1 = j[c1];
-      sr += a0.x * b0.x - a0.y * b0.y + a1.x * b1.x - a1.y * b1.y;
-      si += a0.x * b0.y + a0.y * b0.x + a1.x * b1.y + a1.y * b1.x;
-    }
-    sr = wave_sum(sr);
-    si = wave_sum(si);
-  } else if (lane == 0) {
+    sr = row_sum<LPR, F64>(sr);
+    si = row_sum<LPR, F64>(si);
+  } else if (live && lane == 0) {
     const C2<T> a = reinterpret_cast<const C2<T>*>(a_dense)[m];
     sr = a.x;
     si = a.y;
   }
-  if (lane == 0) {
+  if (live && lane == 0) {
     const C2<T>* phi = reinterpret_cast<const C2<T>*>(phiv);
     const C2<T>* e = reinterpret_cast<const C2<T>*>(ev);
     if (AIM) reinterpret_cast<C2<T>*>(av)[m] = {sr, si};
@@ -724,10 +767,11 @@ __global__ void __launch_bounds__(256) k_zsparse(const int64_t* __restrict__ ptr
 TileQueue phase_queue(Ctx& c, int phase, int ctr) {
   TileQueue q;
   q.tiles = c.d_tiles.as<int4>();
-  q.start = c.d_slot_start.as<int32_t>() + size_t(phase) * (c.slots + 1);
+  q.start = c.d_slot_start.as<int32_t>() + (phase == 0 ? 0 : size_t(c.slots + 1));
   q.ctr = c.dynamic ? c.d_qctr.as<unsigned long long>() + ctr : nullptr;
   q.first = c.phase_first[phase];
   q.count = c.phase_count[phase];
+  q.nslots = phase == 0 ? c.slots : c.zslots();
   return q;
 }
 
@@ -749,10 +793,13 @@ void internal_launch(Ctx& c, const void* H, void* e, void* j, void* g, hipStream
     return;
   }
   unsigned long long* st = c.record ? c.d_stamps.as<unsigned long long>() : nullptr;
-  unsigned long long* sp = c.gprof_on ? c.d_span.as<unsigned long long>() + 2 * size_t(c.slots) * phase : nullptr;
-  const TileQueue q = phase_queue(c, phase, phase);
+  unsigned long long* sp = c.gprof_on ? c.d_span.as<unsigned long long>() + 2 * size_t(phase == 0 ? 0 : c.slots) : nullptr;
+  // the FP64 rows of Z_i on a grid of their own take a counter of their own
+  const bool own = phase == 1 && c.zgrid(F64) != c.zslots();
+  const TileQueue q = phase_queue(c, phase, own ? 4 : phase);
+  const unsigned nwg = unsigned(phase == 0 ? c.slots : c.zgrid(F64));
   auto go = [&](auto kern) {
-    hipLaunchKernelGGL(kern, dim3(unsigned(c.slots)), dim3(256), 0, s, c.d_hi.as<float2>(), c.d_lo.as<float2>(),
+    hipLaunchKernelGGL(kern, dim3(nwg), dim3(256), 0, s, c.d_hi.as<float2>(), c.d_lo.as<float2>(),
                        c.d_blocks.as<BlockDev>(), q, H, e, j, g, st, sp);
   };
   if (F64) go(k_internal<true, 4>);
@@ -796,7 +843,7 @@ void matvec_t(Ctx& c, const void* x, void* y, void* e_out, void* g_out, void* a_
                        F64 ? c.d_pt_w64.p : c.d_pt_w32.p, c.n_pt_nodes, nullptr, rho, oct_in, N3);
     SLIM_HIP(hipGetLastError());
     aim_convolve(c, F64, 1, st, 3, c.layered);
-    hipLaunchKernelGGL(k_phi<F64>, dim3(nblk(nt, 4)), dim3(256), 0, st, c.d_wt_base.as<int32_t>(),
+    hipLaunchKernelGGL(k_phi<F64>, dim3(nblk(nt, 16)), dim3(256), 0, st, c.d_wt_base.as<int32_t>(),
                        F64 ? c.d_wt_w64.p : c.d_wt_w32.p, c.d_oct_out.p, N3, Nx, NxNy, c.d_nP_ptr.as<int64_t>(),
                        c.d_nP_col.as<int32_t>(), F64 ? c.d_nP_v128.p : c.d_nP_v64.p, rho, c.d_phi.p, nt);
     SLIM_HIP(hipGetLastError());
@@ -831,7 +878,7 @@ void matvec_t(Ctx& c, const void* x, void* y, void* e_out, void* g_out, void* a_
     hipLaunchKernelGGL(k_dense_gemv<F64>, dim3(nblk(ne, 4)), dim3(256), 0, s, c.d_LA_hi.as<float2>(),
                        c.d_LA_lo.as<float2>(), ne, jv, nullptr, c.d_a.p);
     SLIM_HIP(hipGetLastError());
-    hipLaunchKernelGGL((k_rows_A<F64, false>), dim3(nblk(ne, 4)), dim3(256), 0, s, nullptr, nullptr, nullptr,
+    hipLaunchKernelGGL((k_rows_A<F64, false>), dim3(nblk(ne, 16)), dim3(256), 0, s, nullptr, nullptr, nullptr,
                        int64_t(0), 0, 0, nullptr, nullptr, nullptr, nullptr, c.d_a.p, c.d_phi.p, ev,
                        c.d_tplus.as<int32_t>(), c.d_tminus.as<int32_t>(), c.d_len.as<double>(),
                        c.d_ix_col.as<int32_t>(), c.d_ix_val.as<double>(), c.k0, inv_eta0, nullptr, Y, ne);
@@ -851,7 +898,7 @@ void matvec_t(Ctx& c, const void* x, void* y, void* e_out, void* g_out, void* a_
     if (overlap) {
       SLIM_HIP(hipStreamWaitEvent(s, c.ev_join, 0));
     } else {
-      hipLaunchKernelGGL(k_phi<F64>, dim3(nblk(nt, 4)), dim3(256), 0, s, c.d_wt_base.as<int32_t>(),
+      hipLaunchKernelGGL(k_phi<F64>, dim3(nblk(nt, 16)), dim3(256), 0, s, c.d_wt_base.as<int32_t>(),
                          F64 ? c.d_wt_w64.p : c.d_wt_w32.p, c.d_oct_out.p, N3, Nx, NxNy, c.d_nP_ptr.as<int64_t>(),
                          c.d_nP_col.as<int32_t>(), F64 ? c.d_nP_v128.p : c.d_nP_v64.p, rho, c.d_phi.p, nt);
       SLIM_HIP(hipGetLastError());
@@ -859,7 +906,7 @@ void matvec_t(Ctx& c, const void* x, void* y, void* e_out, void* g_out, void* a_
     mark(3);
     if (overlap_z) SLIM_HIP(hipStreamWaitEvent(s, c.ev_zjoin, 0));
     mark(4);
-    hipLaunchKernelGGL((k_rows_A<F64, true>), dim3(nblk(ne, 4)), dim3(256), 0, s, c.d_we_base.as<int32_t>(),
+    hipLaunchKernelGGL((k_rows_A<F64, true>), dim3(nblk(ne, 16)), dim3(256), 0, s, c.d_we_base.as<int32_t>(),
                        F64 ? c.d_we_w64.p : c.d_we_w32.p, c.d_oct_out.p, N3, Nx, NxNy, c.d_nA_ptr.as<int64_t>(),
                        c.d_nA_col.as<int32_t>(), F64 ? c.d_nA_v128.p : c.d_nA_v64.p, jv, nullptr, c.d_phi.p,
                        ev, c.d_tplus.as<int32_t>(), c.d_tminus.as<int32_t>(), c.d_len.as<double>(),
@@ -990,7 +1037,8 @@ void matvec_graph(Ctx& c, slim_prec prec, const void* x, void* y, hipStream_t s)
   SLIM_HIP(hipEventSynchronize(c.gev[1]));
   float t_all = 0.f;
   SLIM_HIP(hipEventElapsedTime(&t_all, c.gev[0], c.gev[1]));
-  std::vector<unsigned long long> st(4 * size_t(c.slots));
+  const int zg = c.zgrid(prec == SLIM_FP64);
+  std::vector<unsigned long long> st(2 * size_t(c.slots + zg));
   SLIM_HIP(hipMemcpy(st.data(), c.d_span.p, st.size() * 8, hipMemcpyDeviceToHost));
   if (c.wall_khz <= 0) {
     int khz = 0;
@@ -1002,9 +1050,10 @@ void matvec_graph(Ctx& c, slim_prec prec, const void* x, void* y, hipStream_t s)
   for (int ph = 0; ph < 2; ++ph) {
     if (c.phase_count[ph] == 0) continue;   // no persistent launch (the sparse Z~ rows)
     unsigned long long t0 = ~0ull, t1 = 0;
-    for (int k = 0; k < c.slots; ++k) {
-      t0 = std::min(t0, st[2 * (size_t(ph) * c.slots + k)]);
-      t1 = std::max(t1, st[2 * (size_t(ph) * c.slots + k) + 1]);
+    const size_t base = ph == 0 ? 0 : size_t(c.slots);
+    for (int k = 0; k < (ph == 0 ? c.slots : zg); ++k) {
+      t0 = std::min(t0, st[2 * (base + k)]);
+      t1 = std::max(t1, st[2 * (base + k) + 1]);
     }
     c.gprof_ms[2 + ph] += t1 > t0 && c.wall_khz > 0 ? double(t1 - t0) / double(c.wall_khz) : 0.0;
     a0 = std::min(a0, t0);
@@ -1117,7 +1166,9 @@ void matvec_block(Ctx& c, slim_prec prec, const void* X, void* Y, int R, hipStre
   for (int col0 = 0; col0 < R; col0 += 64) {
     const int ncol = std::min(64, R - col0), ncg = (ncol + 15) / 16;
     auto go = [&](auto kern) {
-      hipLaunchKernelGGL(kern, dim3(unsigned(c.slots)), dim3(256), 0, s, c.d_hi.as<float2>(), c.d_blocks.as<BlockDev>(),
+      // every static queue of both phases has its workgroup (the phases may differ in count)
+      hipLaunchKernelGGL(kern, dim3(unsigned(std::max(c.slots, c.zslots()))), dim3(256), 0, s, c.d_hi.as<float2>(),
+                         c.d_blocks.as<BlockDev>(),
                          phase_queue(c, 0, 2), phase_queue(c, 1, 3), c.d_blk_hoff.as<int64_t>(),
                          Hs, plane, c.blk_cols, col0, c.d_blk_h64.as<float2>() + int64_t(col0) * ne,
                          ne, ncol, c.d_blk_e.as<float2>() + int64_t(col0) * ne, c.d_blk_j.as<float2>() + int64_t(col0) * ne);

@@ -43,13 +43,14 @@ void pack_tiles(Ctx& c, int mode) {
   c.drop_graphs();   // captured products point at the old queues
   const int nb = int(c.blocks.size());
   SLIM_REQUIRE(c.slots > 0, SLIM_E_STATE, "slot count not set");
-  const int S = c.slots;
   const bool learned = (mode == 1 || mode == 4) && !c.mlp_params.empty();
   struct Task { int block, row0, rows; double cost; };
   c.tiles.clear();
-  c.slot_start.assign(2 * size_t(S + 1), 0);
+  c.slot_start.assign(size_t(c.slots + 1) + size_t(c.zslots() + 1), 0);
   for (int phase = 0; phase < 2; ++phase) {
-    // phase 0: rows [n, 2n) of every block (M_i); phase 1: rows [0, n) (Z_i)
+    // phase 0: rows [n, 2n) of every block (M_i); phase 1: rows [0, n) (Z_i), on its own
+    // number of workgroups (fewer leave room for the FFT passes that run beside it)
+    const int S = phase == 0 ? c.slots : c.zslots();
     std::vector<Task> tasks;
     double total = 0.0;
     for (int i = 0; i < nb; ++i) total += c.blocks[i].n * double((c.blocks[i].n + 1) & ~1);
@@ -75,7 +76,7 @@ void pack_tiles(Ctx& c, int mode) {
       }
     }
     const size_t first = c.tiles.size();
-    int32_t* ss = c.slot_start.data() + size_t(phase) * (S + 1);
+    int32_t* ss = c.slot_start.data() + (phase == 0 ? 0 : size_t(c.slots + 1));
     ss[0] = int32_t(first);
     if (mode == 2) {
       // naive: round robin in generation order; slot s's queue is contiguous
@@ -132,8 +133,10 @@ void pack_tiles(Ctx& c, int mode) {
   c.d_tiles.upload(flat);
   c.d_slot_start.upload(c.slot_start);
   c.d_stamps.alloc(std::max<size_t>(1, 2 * c.tiles.size()) * sizeof(unsigned long long));
-  c.d_span.alloc(4 * size_t(S) * sizeof(unsigned long long));
-  c.d_qctr.upload(std::vector<unsigned long long>(4, 0ull));
+  c.d_span.alloc(2 * size_t(c.slots + std::max(c.slots, c.zslots())) * sizeof(unsigned long long));
+  // one ticket counter per (queue, grid size): a launch takes exactly count + grid
+  // tickets, so a counter keeps its meaning only while its launches keep one grid size
+  c.d_qctr.upload(std::vector<unsigned long long>(5, 0ull));
   c.sched_mode = mode;
 }
 

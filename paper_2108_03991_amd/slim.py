@@ -34,7 +34,7 @@ class BuildOpts(C.Structure):
                 ("mem_budget", C.c_int64), ("verbose", C.c_int32), ("use_graphs", C.c_int32),
                 ("precond", C.c_int32), ("precond_overlap", C.c_int32), ("precond_cap", C.c_int64),
                 ("precond_budget", C.c_int64), ("fft_zblock", C.c_int32), ("rows_per_wave", C.c_int32),
-                ("tune_cache", C.c_char_p), ("hf_radius", C.c_double)]
+                ("tune_cache", C.c_char_p), ("hf_radius", C.c_double), ("slots_z", C.c_int32)]
 
 
 class Layout(C.Structure):
@@ -44,7 +44,7 @@ class Layout(C.Structure):
                 ("n_tiles", C.c_int64), ("slots", C.c_int32), ("tile_rows", C.c_int32), ("mean_edge", C.c_double),
                 ("build_seconds", C.c_double), ("device_bytes", C.c_int64), ("precond_blocks", C.c_int64),
                 ("precond_entries", C.c_int64), ("precond_cap", C.c_int64), ("fft_zblock", C.c_int32),
-                ("rows_per_wave", C.c_int32), ("z_nnz", C.c_int64)]
+                ("rows_per_wave", C.c_int32), ("z_nnz", C.c_int64), ("slots_z", C.c_int32)]
 
 
 class SolveOpts(C.Structure):
@@ -125,6 +125,7 @@ def lib():
         L.slim_sched_tiles.argtypes = [vp, dp, C.POINTER(i64)]
         L.slim_sched_train.argtypes = [vp, i32, C.c_double, dp]
         L.slim_sched_set_mode.argtypes = [vp, i32]
+        L.slim_sched_set_shape.argtypes = [vp, i32, i32]
         L.slim_mlp_forward_backward.argtypes = [i32, i32, vp, vp, vp, vp, vp, vp, vp]
         L.slim_mlp_forward_backward_noalloc.argtypes = [i32, i32, vp, vp, vp, vp, vp, vp, vp]
         L.slim_aim_convolve.argtypes = [vp, i32, vp, vp, i32, vp]
@@ -147,7 +148,8 @@ def lib():
         for name in ("slim_create", "slim_set_mesh", "slim_set_materials", "slim_build", "slim_get_layout",
                      "slim_get_rwg", "slim_matvec", "slim_matvec_parts", "slim_internal_apply",
                      "slim_rhs_planewave", "slim_solve", "slim_sched_record", "slim_sched_tiles",
-                     "slim_sched_train", "slim_sched_set_mode", "slim_mlp_forward_backward", "slim_profile",
+                     "slim_sched_train", "slim_sched_set_mode", "slim_sched_set_shape", "slim_mlp_forward_backward",
+                     "slim_profile",
                      "slim_profile_read", "slim_aim_convolve", "slim_get_aim", "slim_get_near",
                      "slim_precond_apply", "slim_get_precond", "slim_precond_partition", "slim_set_medium",
                      "slim_aim_convolve_layered", "slim_get_layered_kernels", "slim_layered_gammas",
@@ -161,7 +163,8 @@ def lib():
 EXPORTS = ["slim_default_build_opts", "slim_create", "slim_destroy", "slim_last_error", "slim_set_mesh",
            "slim_set_materials", "slim_build", "slim_get_layout", "slim_get_rwg", "slim_matvec",
            "slim_matvec_parts", "slim_internal_apply", "slim_rhs_planewave", "slim_solve", "slim_sched_record",
-           "slim_sched_tiles", "slim_sched_train", "slim_sched_set_mode", "slim_mlp_forward_backward",
+           "slim_sched_tiles", "slim_sched_train", "slim_sched_set_mode", "slim_sched_set_shape",
+           "slim_mlp_forward_backward",
            "slim_profile", "slim_profile_read", "slim_aim_convolve", "slim_get_aim", "slim_get_near",
            "slim_precond_apply", "slim_get_precond", "slim_precond_partition", "slim_set_medium",
            "slim_aim_convolve_layered", "slim_get_layered_kernels", "slim_layered_gammas", "slim_matvec_block",
@@ -417,6 +420,9 @@ class Context:
 
     def sched_set_mode(self, mode):
         self._check(lib().slim_sched_set_mode(self._h, int(mode)))
+
+    def sched_set_shape(self, slots, slots_z=0):
+        self._check(lib().slim_sched_set_shape(self._h, int(slots), int(slots_z)))
 
 
 def precond_partition(verts, tris, obj, n_obj, cap, overlap):

@@ -232,24 +232,26 @@ def test_graph_replay_matches_eager(boxes_case):
 
 
 def test_autotune_cache_round_trip(tmp_path, boxes_case):
-    """The autotuner times every (slots per CU, FFT z block, rows per wave) candidate
-    once, writes its choice to the cache keyed by (kernel, shape, architecture), and a second
-    build of the same shape reads it back without timing; the tuned product matches the
-    oracle like any other."""
+    """The autotuner times every (slots per CU, workgroups of the Z_i rows, FFT z block, rows
+    per wave) candidate, writes its choice to the cache keyed by (kernel, shape,
+    architecture), and a second build of the same shape reads it back without timing; the
+    tuned product matches the oracle like any other."""
     path = tmp_path / "tune.txt"
     m = boxes_case[0]
     ctx, lay = context(m, freq=10e9, grid=(16, 16, 16), precond=0, tune_cache=str(path))
     lines = path.read_text().splitlines()
     assert len(lines) == 1 and lines[0].startswith("product|gfx950|")
     assert lay.fft_zblock in (1, 8) and lay.rows_per_wave in (4, 8) and lay.slots % 256 == 0
+    assert lay.slots_z in (lay.slots, 256) and "|z_per_cu=" in lines[0] and "|queues=static|" in lines[0]
     ctx2, lay2 = context(m, freq=10e9, grid=(16, 16, 16), precond=0, tune_cache=str(path))
     assert path.read_text().splitlines() == lines                  # read back, nothing re-timed
-    assert (lay2.slots, lay2.fft_zblock, lay2.rows_per_wave) == (lay.slots, lay.fft_zblock, lay.rows_per_wave)
+    assert (lay2.slots, lay2.slots_z, lay2.fft_zblock, lay2.rows_per_wave) == (lay.slots, lay.slots_z, lay.fft_zblock,
+                                                                                lay.rows_per_wave)
     x = random_complex(lay2.n_sys, 6)
     _check(run_parts(ctx2, lay2, MIXED, x), _oracle_aim_parts(boxes_case, x), lay2.n_e, MIXED, boxes_case[1])
     # explicit shapes are taken as given, without timing
     ctx3, lay3 = context(m, freq=10e9, grid=(16, 16, 16), precond=0, slots=300, fft_zblock=1, rows_per_wave=4)
-    assert (lay3.slots, lay3.fft_zblock, lay3.rows_per_wave) == (300, 1, 4)
+    assert (lay3.slots, lay3.slots_z, lay3.fft_zblock, lay3.rows_per_wave) == (300, 300, 1, 4)
     _check(run_parts(ctx3, lay3, MIXED, x), _oracle_aim_parts(boxes_case, x), lay3.n_e, MIXED, boxes_case[1])
 
 

@@ -176,3 +176,83 @@ def test_learned_packing_held_out():
     print("held-out makespan ms naive %.3f lpt %.3f mlp %.3f (gain of the model over LPT %.1f %%; %d training tiles)"
           % (times[2], times[0], times[1], 100 * (times[0] / times[1] - 1), len(data)))
     assert times[1] <= times[0] * 1.02
+
+
+def test_fewer_workgroups_for_the_z_rows():
+    """The launch of the rows of Z_i on fewer workgroups than the rows of M_i (the shape the
+    autotuner may pick so that the FFT's workgroups fit beside it), in static and dynamic
+    modes: every row covered once, the same product bit for bit in every mode, and the
+    product of a build with equal counts to the bound of two builds (the interior assembly
+    sums with atomic adds, so builds agree to rounding amplified by the interior condition
+    numbers, not bit for bit)."""
+    from tests.gpu_util import rel
+    m = conductors_c5(seed=4, n_obj=160)
+    ref_ctx, ref_lay = context(m, freq=5e9, grid=(32, 32, 32), slots=256, precond=0)
+    x = random_complex(ref_lay.n_sys, 11)
+    ref = {prec: run_parts(ref_ctx, ref_lay, prec, x) for prec in (0, 1)}
+    ref_ctx.close()
+    ctx, lay = context(m, freq=5e9, grid=(32, 32, 32), slots=256, slots_z=96, precond=0)
+    assert (lay.slots, lay.slots_z) == (256, 96)
+    first = {}
+    for mode in (0, 2, 3):
+        ctx.sched_set_mode(mode)
+        t = ctx.sched_tiles()
+        _check_cover(t)
+        if mode != 3:
+            z = t[t[:, 1] < t[:, 3]]
+            assert z[:, 4].max() < 96                 # the rows of Z_i go to the first 96 slots
+        for prec, tol in ((0, 1e-6), (1, 1e-5)):      # FP64: g and y carry Y_eq (cond(L_k0) ~ 1e9)
+            got = run_parts(ctx, lay, prec, x)
+            first.setdefault(prec, got)
+            assert all(np.array_equal(got[k], first[prec][k]) for k in got), (mode, prec)
+            for k in ("e", "g", "y"):
+                assert rel(got[k], ref[prec][k]) <= tol, (mode, prec, k, rel(got[k], ref[prec][k]))
+
+
+def test_set_shape_keeps_the_product():
+    """Re-shaping the two launches after the build (slim_sched_set_shape) re-packs the
+    queues and leaves the product unchanged bit for bit, in static and dynamic modes and in
+    both precisions -- including the FP64 rows of Z_i, which under dynamic dispatch take the
+    M rows' workgroup count and a ticket counter of their own, over repeated products.  A
+    Z launch wider than the M launch keeps the block product on the matrix cores correct
+    (its grid covers both phases' queues).  Bad shapes are argument errors."""
+    import torch
+    from paper_2108_03991_amd import slim
+    from tests.gpu_util import rel
+    m = conductors_c5(seed=4, n_obj=160)
+    ctx, lay = context(m, freq=5e9, grid=(32, 32, 32), slots=256, precond=0)
+    x = random_complex(lay.n_sys, 12)
+    ref = {prec: run_parts(ctx, lay, prec, x) for prec in (0, 1)}
+    for mode in (0, 3):
+        ctx.sched_set_mode(mode)
+        for slots, slots_z in ((512, 128), (256, 512), (384, 0)):
+            ctx.sched_set_shape(slots, slots_z)
+            assert (ctx.layout().slots, ctx.layout().slots_z) == (slots, slots_z or slots)
+            _check_cover(ctx.sched_tiles())
+            for prec in (0, 1):
+                for rep in range(2):
+                    got = run_parts(ctx, lay, prec, x)
+                    assert all(np.array_equal(got[k], ref[prec][k]) for k in got), (mode, slots, slots_z, prec, rep)
+                    xt = torch.tensor(x, device="cuda")         # the captured product (Z rows beside the FFT)
+                    y = torch.zeros_like(xt)
+                    ctx.matvec(prec, xt, y)
+                    torch.cuda.synchronize()
+                    assert np.array_equal(y.cpu().numpy(), ref[prec]["y"]), (mode, slots, slots_z, prec, rep)
+            if (slots, slots_z) == (256, 512):
+                R = 5
+                X = torch.tensor(np.stack([random_complex(lay.n_sys, 40 + q) for q in range(R)]), device="cuda")
+                Y = torch.zeros_like(X)
+                ctx.matvec_block(1, X, Y, R)
+                torch.cuda.synchronize()
+                for q in range(R):
+                    one = run_parts(ctx, lay, 0, X[q].cpu().numpy())["y"]
+                    assert rel(Y[q].cpu().numpy(), one) <= 1e-5, (mode, q)
+    for bad in ((0, 0), (-4, 0), (256, -1), (1 << 17, 0)):
+        with pytest.raises(slim.SlimError) as ei:
+            ctx.sched_set_shape(*bad)
+        assert ei.value.code == 1
+    fresh = slim.Context(0)
+    with pytest.raises(slim.SlimError) as ei:
+        fresh.sched_set_shape(256, 0)
+    assert ei.value.code == 3
+    fresh.close()
