@@ -601,6 +601,19 @@ def main():
                     tune_cache=args.tune_cache)
     log("build: %.1f s, n_e %d n_t %d nnzA %d nnzP %d tiles %d slots %d" % (
         time.time() - t0, lay.n_e, lay.n_t, lay.nnz_near_A, lay.nnz_near_phi, lay.n_tiles, lay.slots))
+    # generation of the interior blocks (eq. (4)-(6)): per object two FP64 LU
+    # factorizations (16/3 n^3 real flops each), two solves with n right-hand sides (8 n^3
+    # each) and the product M = Y_eq Z (8 n^3); n_i from the RWG table (edges by the
+    # object of their T+)
+    _, tplus, _ = ctx.rwg(lay.n_e)
+    n_i = np.bincount(np.asarray(mesh.obj)[tplus], minlength=lay.n_obj).astype(np.float64)
+    gen_flops = float(np.sum((2 * 16.0 / 3.0 + 2 * 8.0 + 8.0) * n_i ** 3))
+    gen = {"seconds": lay.interior_seconds, "workers": lay.interior_workers, "objects": lay.n_obj,
+           "objects_per_s": lay.n_obj / lay.interior_seconds if lay.interior_seconds > 0 else None,
+           "fp64_flops_est": gen_flops,
+           "fp64_tflops_est": gen_flops / lay.interior_seconds / 1e12 if lay.interior_seconds > 0 else None,
+           "largest_n": int(n_i.max())}
+    log("interior generation: %s" % gen)
     n = lay.n_sys
     x = torch.tensor(random_complex(n, 7), dtype=torch.complex128, device="cuda")
     y = torch.zeros_like(x)
@@ -722,6 +735,7 @@ def main():
             "tiles": lay.n_tiles, "slots": lay.slots, "build_s": lay.build_seconds,
             "sched_mode": args.sched,
         },
+        "interior_generation": gen,
         "fp64": {"value": args.steps / dt_fp64, "unit": "matvecs/s", "ms_per_step": 1e3 * dt_fp64 / args.steps,
                  "median_ms_per_step": step_ms["fp64"], "stage_ms": st_fp64 if staged else None,
                  "graph_path_ms": graph_ms["fp64"]},

@@ -134,6 +134,12 @@ typedef struct {
   double hf_radius;
   int32_t slots_z;        /* with slots > 0: persistent workgroups of the launch of the
                              rows of Z_i (0 = slots); ignored when slots = 0 (tuned)  */
+  int32_t gen_workers;    /* concurrent streams (each driven by a host thread of its
+                             own) of the interior-block generation, eq. (4)-(6): the
+                             objects go out in decreasing size, each to the first free
+                             worker; objects whose FP64 work buffers (3 n_i^2 x 16 bytes)
+                             do not fit the free memory once per worker go first, one
+                             at a time.  0 = 8; SLIM_E_ARG below 0 or above 64.      */
 } slim_build_opts;
 
 /* Fill `o` with the defaults used by the tests (near_cheb 3, n_far 4, n_near 5,
@@ -171,6 +177,8 @@ typedef struct {
   int32_t slots_z;                     /* persistent workgroups of the launch of the rows of
                                           Z_i (tuned with the slot count; it runs beside the
                                           projection and FFT of j)                   */
+  int32_t interior_workers;            /* streams the interior-block generation used   */
+  double interior_seconds;             /* its wall time (part of build_seconds)        */
 } slim_layout;
 
 typedef struct {

@@ -5,8 +5,14 @@
 #include <rocsolver/rocsolver.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cstdio>
+#include <exception>
+#include <memory>
+#include <mutex>
+#include <numeric>
+#include <thread>
 #include <unordered_map>
 
 #include "ctx.hpp"
@@ -201,10 +207,14 @@ template <class T> void up(DevBuf& b, const std::vector<T>& v) { b.upload(v); }
 
 // Solve A X = B (n x n, column-major) from rocSOLVER's LU factors of A (in LU,
 // pivots ipiv): row swaps, unit-lower solve (rocBLAS), then a blocked upper solve
-// by substitution on 32-row diagonal blocks with GEMM updates of the rows above.
-// The interior EFIE matrices at low frequency have pivots spanning about eight
-// decades; explicit inversion of diagonal blocks (as in rocBLAS TRSM) loses all
-// accuracy on such factors, substitution does not.
+// by substitution on 32-row diagonal blocks.  The interior EFIE matrices at low
+// frequency have pivots spanning about eight decades; explicit inversion of
+// diagonal blocks (as in rocBLAS TRSM) loses all accuracy on such factors,
+// substitution does not.  The updates are two-level: inside a 256-row panel the
+// rows above each solved 32-row block are updated by a narrow GEMM restricted to
+// the panel, and the rows above the panel by one GEMM with inner dimension 256 once
+// the panel is solved, so the large updates read and write X once per 256 solved
+// rows instead of once per 32 (the same sums, grouped differently).
 // B has nrhs columns (leading dimension n).
 void lu_solve_rhs(rocblas_handle h, int n, double* LU, const rocblas_int* ipiv, double* B, int nrhs, hipStream_t s) {
   auto Z = [](double* p) { return reinterpret_cast<rocblas_double_complex*>(p); };
@@ -212,14 +222,22 @@ void lu_solve_rhs(rocblas_handle h, int n, double* LU, const rocblas_int* ipiv, 
   rocblas_double_complex one{1.0, 0.0}, mone{-1.0, 0.0};
   SLIM_ROC(rocblas_ztrsm(h, rocblas_side_left, rocblas_fill_lower, rocblas_operation_none, rocblas_diagonal_unit, n,
                          nrhs, &one, Z(LU), n, Z(B), n));
-  const int nb = 32;
-  for (int i1 = n; i1 > 0;) {
-    const int i0 = std::max(0, i1 - nb);
-    launch_usolve_block(LU, n, i0, i1 - i0, B, n, nrhs, s);
-    if (i0 > 0)
-      SLIM_ROC(rocblas_zgemm(h, rocblas_operation_none, rocblas_operation_none, i0, nrhs, i1 - i0, &mone,
-                             Z(LU) + int64_t(i0) * n, n, Z(B) + i0, n, &one, Z(B), n));
-    i1 = i0;
+  // X[r0:r1) -= U[r0:r1, c0:c1) X[c0:c1)
+  auto update = [&](int r0, int r1, int c0, int c1) {
+    SLIM_ROC(rocblas_zgemm(h, rocblas_operation_none, rocblas_operation_none, r1 - r0, nrhs, c1 - c0, &mone,
+                           Z(LU) + int64_t(c0) * n + r0, n, Z(B) + c0, n, &one, Z(B) + r0, n));
+  };
+  const int nb = 32, NB = 256;
+  for (int j1 = n; j1 > 0;) {
+    const int j0 = std::max(0, j1 - NB);
+    for (int i1 = j1; i1 > j0;) {
+      const int i0 = std::max(j0, i1 - nb);
+      launch_usolve_block(LU, n, i0, i1 - i0, B, n, nrhs, s);
+      if (i0 > j0) update(j0, i0, i0, i1);
+      i1 = i0;
+    }
+    if (j0 > 0) update(0, j0, j0, j1);
+    j1 = j0;
   }
 }
 
@@ -242,9 +260,126 @@ Ctx::~Ctx() {
   if (s_int) (void)hipStreamDestroy(s_int);
 }
 
+namespace {
+
+// One stream of the interior-block generation, driven by a host thread of its own:
+// FP64 work buffers for blocks up to order `cap`, a rocBLAS handle on the stream, and
+// grow-only buffers for the per-object lists.
+struct GenWorker {
+  hipStream_t s = nullptr;
+  std::unique_ptr<RocHandle> rh;
+  DevBuf L, B, Z, ipiv, pairs, zrow, zcol, zval;
+  void open(int device, int64_t cap) {
+    SLIM_HIP(hipSetDevice(device));
+    SLIM_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    rh.reset(new RocHandle(s));
+    const size_t blk = size_t(cap) * size_t(cap) * 16;
+    L.alloc(blk);
+    B.alloc(blk);
+    Z.alloc(blk);
+    ipiv.alloc(size_t(std::max<int64_t>(1, cap)) * sizeof(rocblas_int));
+  }
+  ~GenWorker() {
+    rh.reset();
+    if (s) (void)hipStreamDestroy(s);
+  }
+};
+
+// Copy a host list to a device buffer on stream s (grown, never shrunk, so that
+// reallocations, which synchronize the device, stay rare); the host data must stay
+// alive until the stream has been synchronized.
+template <class T> void upload_on(DevBuf& b, const std::vector<T>& v, hipStream_t s) {
+  const size_t bytes = v.size() * sizeof(T);
+  if (b.bytes < bytes) b.alloc(std::max(bytes, b.bytes + b.bytes / 2));
+  if (bytes) SLIM_HIP(hipMemcpyAsync(b.p, v.data(), bytes, hipMemcpyHostToDevice, s));
+}
+
+// What every object's generation shares (read-only while the workers run).
+struct GenShared {
+  const Ctx* c;
+  AsmLaunch base;                              // geometry pointers
+  rocblas_int* info;                           // 2 per object: L_kc, L_k0 factorizations
+  bool hf;
+  const std::vector<std::vector<int32_t>>* z_rows;
+  const std::vector<std::vector<int32_t>>* z_cols;
+  const std::vector<int64_t>* z_off;           // first entry of each object's Z~ in the CSR
+};
+
+// Z_i, M_i = Y_eq,i Z_i of object i into the arena (and its Z~ entries with the
+// sparse interior operators), on the worker's stream; returns when they are written.
+void gen_object(const GenShared& g, GenWorker& w, int i) {
+  const Ctx& c = *g.c;
+  const RWGTable& r = c.rwg;
+  const int n = c.blocks[i].n;
+  const size_t bytes = size_t(n) * n * 16;
+  hipStream_t s = w.s;
+  rocblas_handle h = w.rh->h;
+  AsmLaunch L = g.base;
+  L.t0 = int32_t(r.obj_tri_off[i]);
+  L.t1 = int32_t(r.obj_tri_off[i + 1]);
+  L.e0 = c.blocks[i].e0;
+  L.ld_e = n;
+  const std::vector<int32_t> pairs = near_candidates(r, L.t0, L.t1, c.opts.c_near);
+  upload_on(w.pairs, pairs, s);
+  L.near_pairs = w.pairs.as<int32_t>();
+  L.n_near_pairs = int64_t(pairs.size() / 2);
+  // ---- Z_i = -1/(j w eps_c) L_kc^{-1} (K_kc + I_x/2)  (eq. (4)) ----
+  SLIM_HIP(hipMemsetAsync(w.L.p, 0, bytes, s));
+  SLIM_HIP(hipMemsetAsync(w.Z.p, 0, bytes, s));
+  L.k = c.kc[i];
+  L.Lk = w.L.as<double>(); L.Kk = w.Z.as<double>(); L.Lvec = nullptr; L.Lphi = nullptr;
+  L.skip_mag = 1e-24;   // conductor kernel: far pairs with |e^{-jk R}| < 1e-24 contribute nothing
+  L.cut_r2 = g.hf ? c.opts.hf_radius * c.opts.hf_radius : 0.0;   // sparse L~, K~: distant pairs ignored
+  launch_assemble(L, s);
+  L.cut_r2 = 0.0;
+  launch_add_scaled_ix(w.Z.as<double>(), c.d_ix_col.as<int32_t>(), c.d_ix_val.as<double>(), L.e0, n, 0.5, s);
+  SLIM_ROC(rocsolver_zgetrf(h, n, n, reinterpret_cast<rocblas_double_complex*>(w.L.p), n, w.ipiv.as<rocblas_int>(),
+                            g.info + 2 * i));
+  lu_solve(h, n, w.L.as<double>(), w.ipiv.as<rocblas_int>(), w.Z.as<double>(), s);
+  cd fz = -1.0 / (cd(0.0, 1.0) * c.omega * c.epsc[i]);
+  launch_scale(w.Z.as<double>(), int64_t(n) * n, fz, s);
+  if (g.hf) {
+    // keep Z~ on its pattern: gather the entries (complex64 hi + lo), then zero the
+    // dense copy off the pattern for M = Y_eq Z~
+    const std::vector<int32_t>& zr = (*g.z_rows)[size_t(i)];
+    const std::vector<int32_t>& zc = (*g.z_cols)[size_t(i)];
+    const int64_t nz = int64_t(zr.size());
+    upload_on(w.zrow, zr, s);
+    upload_on(w.zcol, zc, s);
+    if (w.zval.bytes < size_t(std::max<int64_t>(1, nz)) * 16) w.zval.alloc(size_t(std::max<int64_t>(1, nz)) * 16);
+    const int64_t z0 = (*g.z_off)[size_t(i)];
+    launch_z_gather_mask(w.Z.as<double>(), n, w.zrow.as<int32_t>(), w.zcol.as<int32_t>(), nz, w.zval.as<double>(),
+                         c.d_zs_hi.as<Cplx<float>>() + z0, c.d_zs_lo.as<Cplx<float>>() + z0, s);
+  }
+  // ---- Y_eq,i = 1/(j w mu0) L_k0^{-1} (K_k0 + I_x/2)  (eq. (5), free-space layer) ----
+  SLIM_HIP(hipMemsetAsync(w.L.p, 0, bytes, s));
+  SLIM_HIP(hipMemsetAsync(w.B.p, 0, bytes, s));
+  L.k = cd(c.k0, 0.0);
+  L.Lk = w.L.as<double>(); L.Kk = w.B.as<double>();
+  L.skip_mag = 0.0;
+  launch_assemble(L, s);
+  launch_add_scaled_ix(w.B.as<double>(), c.d_ix_col.as<int32_t>(), c.d_ix_val.as<double>(), L.e0, n, 0.5, s);
+  SLIM_ROC(rocsolver_zgetrf(h, n, n, reinterpret_cast<rocblas_double_complex*>(w.L.p), n, w.ipiv.as<rocblas_int>(),
+                            g.info + 2 * i + 1));
+  lu_solve(h, n, w.L.as<double>(), w.ipiv.as<rocblas_int>(), w.B.as<double>(), s);
+  // ---- M_i = Y_eq,i Z_i  (eq. (6)); the 1/(j w mu0) factor folded into alpha ----
+  cd fy = 1.0 / (cd(0.0, 1.0) * c.omega * kMu0);
+  rocblas_double_complex alpha{fy.real(), fy.imag()}, beta{0.0, 0.0};
+  SLIM_ROC(rocblas_zgemm(h, rocblas_operation_none, rocblas_operation_none, n, n, n, &alpha,
+                         reinterpret_cast<rocblas_double_complex*>(w.B.p), n,
+                         reinterpret_cast<rocblas_double_complex*>(w.Z.p), n, &beta,
+                         reinterpret_cast<rocblas_double_complex*>(w.L.p), n));
+  const int64_t row0 = g.hf ? n : 0;   // sparse mode: only the rows of M_i are stored
+  const int64_t first = c.blocks[i].off + row0 * ((n + 1) & ~1);
+  launch_pack_block(w.Z.as<double>(), w.L.as<double>(), n, int(row0), c.d_hi.as<Cplx<float>>() + first,
+                    c.d_lo.as<Cplx<float>>() + first, s);
+  SLIM_HIP(hipStreamSynchronize(s));   // the host lists above and the work buffers are reused next
+}
+
+}  // namespace
+
 static void build_internal(Ctx& c, hipStream_t s) {
   const RWGTable& r = c.rwg;
-  RocHandle rh(s);
   // arena layout: the 2n x ld rows of [Z_i; M_i] (rows padded to an even length,
   // 16-byte aligned); with sparse interior operators only the n rows of M_i, and a
   // block's offset is that of its (absent) row 0, so rows n..2n-1 sit where they would
@@ -259,125 +394,130 @@ static void build_internal(Ctx& c, hipStream_t s) {
     nmax = std::max(nmax, n);
   }
   c.arena_elems = off;
+  auto workspace = [](int64_t n) { return 3 * n * n * 16; };   // L, B, Z of one worker
   if (c.opts.mem_budget > 0) {
-    int64_t need = off * 16 + 3 * nmax * nmax * 16;
+    int64_t need = off * 16 + workspace(nmax);
     SLIM_REQUIRE(need <= c.opts.mem_budget, SLIM_E_OOM,
                  "device memory budget too small: internal blocks need " + std::to_string(need) + " bytes");
   }
   c.d_hi.alloc(size_t(off) * sizeof(Cplx<float>));
   c.d_lo.alloc(size_t(off) * sizeof(Cplx<float>));
   up(c.d_blocks, c.blocks);
-  DevBuf bufL, bufB, bufZ, ipiv, info;
-  bufL.alloc(size_t(nmax * nmax) * 16);
-  bufB.alloc(size_t(nmax * nmax) * 16);
-  bufZ.alloc(size_t(nmax * nmax) * 16);
-  ipiv.alloc(size_t(nmax) * sizeof(rocblas_int));
+  DevBuf info;
   info.alloc(sizeof(rocblas_int) * size_t(r.n_obj) * 2);
   SLIM_HIP(hipMemsetAsync(info.p, 0, info.bytes, s));
-  QuadOpts qo;
-  AsmLaunch L{};
-  L.xyz = c.d_xyz.as<double>(); L.tri = c.d_tri.as<int32_t>(); L.cen = c.d_cen.as<double>();
-  L.nrm = c.d_nrm.as<double>(); L.area = c.d_area.as<double>(); L.diam = c.d_diam.as<double>();
-  L.tri_edge = c.d_tri_edge.as<int32_t>(); L.tri_sign = c.d_tri_sign.as<int8_t>(); L.len = c.d_len.as<double>();
-  DevBuf d_pairs;
-  // sparse Z~ (hf_radius > 0): CSR over all RWG rows, global columns; per object the
-  // local (row, column) list gathers its entries from the dense FP64 solution
-  std::vector<int64_t> zs_ptr(1, 0);
+  // sparse Z~ (hf_radius > 0): CSR over all RWG rows, global columns, in object order;
+  // per object the local (row, column) list gathers its entries from the dense FP64
+  // solution into its own range of the CSR
+  std::vector<int64_t> zs_ptr(1, 0), z_off(size_t(r.n_obj) + 1, 0);
   std::vector<int32_t> zs_col;
-  DevBuf d_zrow, d_zcol, d_zval;
   if (hf) {
     c.d_zs_hi.release();
     c.d_zs_lo.release();
   }
   std::vector<std::vector<int32_t>> z_rows(hf ? r.n_obj : 0), z_cols(hf ? r.n_obj : 0);
-  int64_t z_total = 0;
   for (int i = 0; hf && i < r.n_obj; ++i) {
-    z_pattern(r, r.obj_tri_off[i], r.obj_tri_off[i + 1], c.blocks[i].e0, c.blocks[i].n, c.opts.hf_radius, z_rows[i],
-              z_cols[i]);
-    z_total += int64_t(z_rows[i].size());
+    const int n = c.blocks[i].n;
+    z_pattern(r, r.obj_tri_off[i], r.obj_tri_off[i + 1], c.blocks[i].e0, n, c.opts.hf_radius, z_rows[i], z_cols[i]);
+    const int64_t nz = int64_t(z_rows[i].size());
+    z_off[size_t(i) + 1] = z_off[size_t(i)] + nz;
+    for (int64_t k = 0; k < nz; ++k) zs_col.push_back(c.blocks[i].e0 + z_cols[i][size_t(k)]);
+    int64_t k = 0;
+    for (int m = 0; m < n; ++m) {
+      while (k < nz && z_rows[i][size_t(k)] == m) ++k;
+      zs_ptr.push_back(z_off[size_t(i)] + k);
+    }
   }
+  const int64_t z_total = z_off.back();
   if (hf) {
     SLIM_REQUIRE(z_total < (int64_t(1) << 40), SLIM_E_UNSUPPORTED, "sparse interior operator too large");
     c.d_zs_hi.alloc(size_t(std::max<int64_t>(1, z_total)) * sizeof(Cplx<float>));
     c.d_zs_lo.alloc(size_t(std::max<int64_t>(1, z_total)) * sizeof(Cplx<float>));
   }
-  int64_t z_done = 0;
-  for (int i = 0; i < r.n_obj; ++i) {
-    const int n = c.blocks[i].n;
-    const size_t bytes = size_t(n) * n * 16;
-    L.t0 = int32_t(r.obj_tri_off[i]);
-    L.t1 = int32_t(r.obj_tri_off[i + 1]);
-    L.e0 = c.blocks[i].e0;
-    L.ld_e = n;
-    std::vector<int32_t> pairs = near_candidates(r, L.t0, L.t1, c.opts.c_near);
-    d_pairs.upload(pairs);
-    L.near_pairs = d_pairs.as<int32_t>();
-    L.n_near_pairs = int64_t(pairs.size() / 2);
-    // ---- Z_i = -1/(j w eps_c) L_kc^{-1} (K_kc + I_x/2)  (eq. (4)) ----
-    SLIM_HIP(hipMemsetAsync(bufL.p, 0, bytes, s));
-    SLIM_HIP(hipMemsetAsync(bufZ.p, 0, bytes, s));
-    L.k = c.kc[i];
-    L.Lk = bufL.as<double>(); L.Kk = bufZ.as<double>(); L.Lvec = nullptr; L.Lphi = nullptr;
-    L.skip_mag = 1e-24;   // conductor kernel: far pairs with |e^{-jk R}| < 1e-24 contribute nothing
-    L.cut_r2 = hf ? c.opts.hf_radius * c.opts.hf_radius : 0.0;   // sparse L~, K~: distant pairs ignored
-    launch_assemble(L, s);
-    L.cut_r2 = 0.0;
-    launch_add_scaled_ix(bufZ.as<double>(), c.d_ix_col.as<int32_t>(), c.d_ix_val.as<double>(), L.e0, n, 0.5, s);
-    SLIM_ROC(rocsolver_zgetrf(rh.h, n, n, reinterpret_cast<rocblas_double_complex*>(bufL.p), n,
-                              ipiv.as<rocblas_int>(), info.as<rocblas_int>() + 2 * i));
-    lu_solve(rh.h, n, bufL.as<double>(), ipiv.as<rocblas_int>(), bufZ.as<double>(), s);
-    cd fz = -1.0 / (cd(0.0, 1.0) * c.omega * c.epsc[i]);
-    launch_scale(bufZ.as<double>(), int64_t(n) * n, fz, s);
-    if (hf) {
-      // keep Z~ on its pattern: gather the entries (complex64 hi + lo, global columns),
-      // then zero the dense copy off the pattern for M = Y_eq Z~
-      const int64_t nz = int64_t(z_rows[i].size());
-      d_zrow.upload(z_rows[i]);
-      d_zcol.upload(z_cols[i]);
-      if (d_zval.bytes < size_t(std::max<int64_t>(1, nz)) * 16) d_zval.alloc(size_t(std::max<int64_t>(1, nz)) * 16);
-      launch_z_gather_mask(bufZ.as<double>(), n, d_zrow.as<int32_t>(), d_zcol.as<int32_t>(), nz, d_zval.as<double>(),
-                           c.d_zs_hi.as<Cplx<float>>() + z_done, c.d_zs_lo.as<Cplx<float>>() + z_done, s);
-      for (int64_t k = 0; k < nz; ++k) zs_col.push_back(c.blocks[i].e0 + z_cols[i][size_t(k)]);
-      int64_t k = 0;
-      for (int m = 0; m < n; ++m) {
-        while (k < nz && z_rows[i][size_t(k)] == m) ++k;
-        zs_ptr.push_back(z_done + k);
+  SLIM_HIP(hipStreamSynchronize(s));
+
+  GenShared g;
+  g.c = &c;
+  AsmLaunch& L = g.base;
+  L = AsmLaunch{};
+  L.xyz = c.d_xyz.as<double>(); L.tri = c.d_tri.as<int32_t>(); L.cen = c.d_cen.as<double>();
+  L.nrm = c.d_nrm.as<double>(); L.area = c.d_area.as<double>(); L.diam = c.d_diam.as<double>();
+  L.tri_edge = c.d_tri_edge.as<int32_t>(); L.tri_sign = c.d_tri_sign.as<int8_t>(); L.len = c.d_len.as<double>();
+  g.info = info.as<rocblas_int>();
+  g.hf = hf;
+  g.z_rows = &z_rows;
+  g.z_cols = &z_cols;
+  g.z_off = &z_off;
+
+  // The objects are handed out in decreasing size -- the list order of LPT (Alg. 1);
+  // any cost estimate that grows with n_i (the LU's n_i^3, the paper's n_i^2) gives
+  // this order -- each to the first worker that is free.  Workers are streams with
+  // host threads of their own, so that the many short kernels of small objects
+  // (panel factorizations, narrow solves) overlap.  Objects whose workspace does not
+  // fit the memory left beside the arena once per worker go first, one at a time.
+  std::vector<int> order(size_t(r.n_obj));
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return c.blocks[a].n > c.blocks[b].n; });
+  size_t freeb = 0, totalb = 0;
+  SLIM_HIP(hipMemGetInfo(&freeb, &totalb));
+  int64_t budget = int64_t(freeb) - (int64_t(4) << 30);   // room for rocBLAS workspaces and the lists
+  if (c.opts.mem_budget > 0) budget = std::min(budget, c.opts.mem_budget - off * 16);
+  budget = std::max(budget, workspace(nmax));
+  const int K = std::max(1, std::min(r.n_obj, c.opts.gen_workers > 0 ? c.opts.gen_workers : 8));
+  size_t split = 0;
+  while (split < order.size() && int64_t(K) * workspace(c.blocks[order[split]].n) > budget) ++split;
+
+  std::atomic<int> done{0};
+  std::mutex print_mu;
+  auto last_print = std::chrono::steady_clock::now();
+  auto run_pool = [&](size_t b0, size_t b1, int workers) {
+    if (b1 <= b0) return;
+    const int64_t cap = c.blocks[order[b0]].n;
+    std::atomic<size_t> next{b0};
+    std::atomic<bool> stop{false};
+    std::exception_ptr err;
+    std::mutex err_mu;
+    auto body = [&]() {
+      try {
+        GenWorker w;
+        w.open(c.device, cap);
+        for (size_t k = next++; k < b1 && !stop; k = next++) {
+          const int i = order[k];
+          gen_object(g, w, i);
+          const int d = ++done;
+          if (c.opts.verbose) {
+            std::lock_guard<std::mutex> lk(print_mu);
+            auto now = std::chrono::steady_clock::now();
+            if (d == r.n_obj || std::chrono::duration<double>(now - last_print).count() > 10.0) {
+              std::fprintf(stderr, "[slim build] interior blocks %d / %d (n = %d)\n", d, r.n_obj, c.blocks[i].n);
+              std::fflush(stderr);
+              last_print = now;
+            }
+          }
+        }
+      } catch (...) {
+        std::lock_guard<std::mutex> lk(err_mu);
+        if (!err) err = std::current_exception();
+        stop = true;
       }
-      z_done += nz;
+    };
+    const int nw = int(std::min<size_t>(size_t(workers), b1 - b0));
+    if (nw == 1) {
+      body();
+    } else {
+      std::vector<std::thread> th;
+      for (int k = 0; k < nw; ++k) th.emplace_back(body);
+      for (std::thread& t : th) t.join();
     }
-    // ---- Y_eq,i = 1/(j w mu0) L_k0^{-1} (K_k0 + I_x/2)  (eq. (5), free-space layer) ----
-    SLIM_HIP(hipMemsetAsync(bufL.p, 0, bytes, s));
-    SLIM_HIP(hipMemsetAsync(bufB.p, 0, bytes, s));
-    L.k = cd(c.k0, 0.0);
-    L.Lk = bufL.as<double>(); L.Kk = bufB.as<double>();
-    L.skip_mag = 0.0;
-    launch_assemble(L, s);
-    launch_add_scaled_ix(bufB.as<double>(), c.d_ix_col.as<int32_t>(), c.d_ix_val.as<double>(), L.e0, n, 0.5, s);
-    SLIM_ROC(rocsolver_zgetrf(rh.h, n, n, reinterpret_cast<rocblas_double_complex*>(bufL.p), n,
-                              ipiv.as<rocblas_int>(), info.as<rocblas_int>() + 2 * i + 1));
-    lu_solve(rh.h, n, bufL.as<double>(), ipiv.as<rocblas_int>(), bufB.as<double>(), s);
-    // ---- M_i = Y_eq,i Z_i  (eq. (6)); the 1/(j w mu0) factor folded into alpha ----
-    cd fy = 1.0 / (cd(0.0, 1.0) * c.omega * kMu0);
-    rocblas_double_complex alpha{fy.real(), fy.imag()}, beta{0.0, 0.0};
-    SLIM_ROC(rocblas_zgemm(rh.h, rocblas_operation_none, rocblas_operation_none, n, n, n, &alpha,
-                           reinterpret_cast<rocblas_double_complex*>(bufB.p), n,
-                           reinterpret_cast<rocblas_double_complex*>(bufZ.p), n, &beta,
-                           reinterpret_cast<rocblas_double_complex*>(bufL.p), n));
-    const int64_t row0 = hf ? n : 0;   // sparse mode: only the rows of M_i are stored
-    const int64_t first = c.blocks[i].off + row0 * ((n + 1) & ~1);
-    launch_pack_block(bufZ.as<double>(), bufL.as<double>(), n, int(row0), c.d_hi.as<Cplx<float>>() + first,
-                      c.d_lo.as<Cplx<float>>() + first, s);
-    SLIM_HIP(hipStreamSynchronize(s));   // the pair list of the next object reuses d_pairs
-    if (c.opts.verbose) {
-      static thread_local auto last = std::chrono::steady_clock::now();
-      auto now = std::chrono::steady_clock::now();
-      if (i + 1 == r.n_obj || std::chrono::duration<double>(now - last).count() > 10.0) {
-        std::fprintf(stderr, "[slim build] interior blocks %d / %d (n = %d)\n", i + 1, r.n_obj, n);
-        std::fflush(stderr);
-        last = now;
-      }
-    }
-  }
+    SLIM_HIP(hipSetDevice(c.device));
+    if (err) std::rethrow_exception(err);
+  };
+  const auto t_gen = std::chrono::steady_clock::now();
+  run_pool(0, split, 1);
+  run_pool(split, order.size(), K);
+  c.gen_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_gen).count();
+  c.gen_workers = split < order.size() ? std::min<int>(K, int(order.size() - split)) : 1;
+
   std::vector<rocblas_int> h_info(2 * size_t(r.n_obj));
   SLIM_HIP(hipMemcpy(h_info.data(), info.p, info.bytes, hipMemcpyDeviceToHost));
   for (int i = 0; i < 2 * r.n_obj; ++i)
@@ -557,6 +697,7 @@ void build_all(Ctx& c, const slim_build_opts& o) {
   SLIM_REQUIRE(std::isfinite(o.hf_radius) && o.hf_radius >= 0.0, SLIM_E_ARG, "hf_radius must be finite and >= 0");
   SLIM_REQUIRE(!(o.hf_radius > 0.0 && o.precond), SLIM_E_UNSUPPORTED,
                "the conductor-block preconditioner needs the dense Z_i rows: build with precond = 0 when hf_radius > 0");
+  SLIM_REQUIRE(o.gen_workers >= 0 && o.gen_workers <= 64, SLIM_E_ARG, "gen_workers must be in [0, 64]");
   SLIM_HIP(hipSetDevice(c.device));
   c.built = false;
   // A new build starts in free space: the reflected kernels, their spectra and the
@@ -691,6 +832,8 @@ void build_all(Ctx& c, const slim_build_opts& o) {
   Lo.rows_per_wave = c.rw_mixed;
   Lo.z_nnz = c.z_nnz;
   Lo.slots_z = c.zslots();
+  Lo.interior_workers = c.gen_workers;
+  Lo.interior_seconds = c.gen_seconds;
   c.built = true;
 }
 

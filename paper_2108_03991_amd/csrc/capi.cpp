@@ -62,6 +62,7 @@ void slim_default_build_opts(slim_build_opts* o) {
   o->tune_cache = nullptr;
   o->hf_radius = 0.0;
   o->slots_z = 0;
+  o->gen_workers = 0;
 }
 
 slim_status slim_create(int32_t hip_device, slim_ctx** out) {

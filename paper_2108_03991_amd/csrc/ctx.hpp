@@ -60,6 +60,8 @@ struct Ctx {
   DevBuf d_hi, d_lo;                    // Cplx<float>
   DevBuf d_blocks;                      // Block[]
   int64_t arena_elems = 0;
+  double gen_seconds = 0.0;             // wall time of the interior-block generation
+  int gen_workers = 0;                  // concurrent streams it used for the smaller objects
 
   // ---- sparse Z~ of the high-frequency form (hf_radius > 0): CSR over all RWG rows,
   //      global columns, hi and lo complex64 values; the arena then holds only M_i ----

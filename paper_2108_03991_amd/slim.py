@@ -34,7 +34,8 @@ class BuildOpts(C.Structure):
                 ("mem_budget", C.c_int64), ("verbose", C.c_int32), ("use_graphs", C.c_int32),
                 ("precond", C.c_int32), ("precond_overlap", C.c_int32), ("precond_cap", C.c_int64),
                 ("precond_budget", C.c_int64), ("fft_zblock", C.c_int32), ("rows_per_wave", C.c_int32),
-                ("tune_cache", C.c_char_p), ("hf_radius", C.c_double), ("slots_z", C.c_int32)]
+                ("tune_cache", C.c_char_p), ("hf_radius", C.c_double), ("slots_z", C.c_int32),
+                ("gen_workers", C.c_int32)]
 
 
 class Layout(C.Structure):
@@ -44,7 +45,8 @@ class Layout(C.Structure):
                 ("n_tiles", C.c_int64), ("slots", C.c_int32), ("tile_rows", C.c_int32), ("mean_edge", C.c_double),
                 ("build_seconds", C.c_double), ("device_bytes", C.c_int64), ("precond_blocks", C.c_int64),
                 ("precond_entries", C.c_int64), ("precond_cap", C.c_int64), ("fft_zblock", C.c_int32),
-                ("rows_per_wave", C.c_int32), ("z_nnz", C.c_int64), ("slots_z", C.c_int32)]
+                ("rows_per_wave", C.c_int32), ("z_nnz", C.c_int64), ("slots_z", C.c_int32),
+                ("interior_workers", C.c_int32), ("interior_seconds", C.c_double)]
 
 
 class SolveOpts(C.Structure):

@@ -273,3 +273,40 @@ def test_graph_path_timing_events(boxes_case):
     torch.cuda.synchronize()
     assert n == 3 and 0 < ms[0] <= ms[1]
     assert torch.equal(y0, y1)
+
+
+def test_generation_workers():
+    """The interior blocks (eq. (4)-(6)) generated by one worker, by eight concurrent
+    workers (the default), and under a memory budget that leaves room for one worker of the
+    largest order only, so that the largest objects go first one at a time and the rest run
+    concurrently: the same operator in every case, to the rounding by which two builds
+    differ (assembly sums with atomic adds; Y_eq carries cond(L_k0) ~ 1e9)."""
+    from inputs.geometry import conductors_c5
+    from paper_2108_03991_amd import slim
+    m = conductors_c5(seed=4, n_obj=160)
+    tri = np.bincount(m.obj, minlength=m.n_obj)
+    assert np.all(tri % 2 == 0)                      # closed surfaces: 3/2 edges per triangle
+    n_max = int(3 * tri.max() // 2)
+    opts = dict(freq=5e9, grid=(32, 32, 32), slots=256, precond=0)
+    ctx1, lay1 = context(m, gen_workers=1, **opts)
+    assert lay1.interior_workers == 1 and 0 < lay1.interior_seconds < lay1.build_seconds
+    x = random_complex(lay1.n_sys, 13)
+    ref = {p: run_parts(ctx1, lay1, p, x) for p in (FP64, MIXED)}
+    ctx1.close()
+    budget = lay1.internal_entries * 16 + 3 * n_max * n_max * 16
+    for kw in (dict(), dict(mem_budget=budget)):
+        ctx, lay = context(m, **opts, **kw)
+        assert lay.interior_workers == 8, kw
+        for p in (FP64, MIXED):
+            got = run_parts(ctx, lay, p, x)
+            assert rel(got["e"], ref[p]["e"]) <= (1e-9 if p == FP64 else 1e-5), (kw, p)
+            for k in ("g", "y"):
+                assert rel(got[k], ref[p][k]) <= (1e-6 if p == FP64 else 1e-5), (kw, p, k)
+        ctx.close()
+    ctx = slim.Context(0)
+    ctx.set_mesh(m.verts, m.tris, m.obj, m.n_obj)
+    for bad in (-1, 65):
+        with pytest.raises(slim.SlimError) as ei:
+            ctx.build(gen_workers=bad, **opts)
+        assert ei.value.code == 1
+    ctx.close()
