@@ -561,6 +561,9 @@ def main():
                     help="only run the layered-medium study and print its JSON")
     ap.add_argument("--no-srr", action="store_true",
                     help="skip the split-ring array (64 SRRs, 100 GHz, AIM 64^3) product rates")
+    ap.add_argument("--gen-workers", type=int, default=0,
+                    help="concurrent streams of the interior-block generation (0 = the library's default); "
+                         "1 keeps the build single-threaded, as profilers that trace every launch need")
     ap.add_argument("--graph-only", action="store_true",
                     help="time the graph path only, without the staged eager breakdown (for kernel traces whose "
                          "per-kernel averages are the graph-path launches)")
@@ -598,7 +601,7 @@ def main():
     # the launch shape is tuned under dynamic dispatch, the queue form of the timed products
     # (modes 3 and 4); the schedule study re-packs the same tiles in every mode
     lay = ctx.build(freq=freq, grid=grid, sched_mode=3, verbose=1, precond=0 if args.no_solve else 1,
-                    tune_cache=args.tune_cache)
+                    tune_cache=args.tune_cache, gen_workers=args.gen_workers)
     log("build: %.1f s, n_e %d n_t %d nnzA %d nnzP %d tiles %d slots %d" % (
         time.time() - t0, lay.n_e, lay.n_t, lay.nnz_near_A, lay.nnz_near_phi, lay.n_tiles, lay.slots))
     # generation of the interior blocks (eq. (4)-(6)): per object two FP64 LU
@@ -753,6 +756,9 @@ def main():
                      "bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK, "traffic": traffic,
                      "algorithmic_bytes_per_launch": 0.5 * bytes_m["internal"],
+                     "traffic_over_algorithmic": (traffic / (0.5 * bytes_m["internal"])) if traffic else None,
+                     "traffic_source": "profiles/hbm_traffic_internal_conductors_2000.md (FETCH_SIZE x 2 + "
+                                       "WRITE_SIZE, bytes per launch)" if traffic else None,
                      "mean_launch_ms": 1e3 * t_int,
                      "measured_copy_GBps": copy_bw / 1e9, "frac_of_measured_copy": achieved / copy_bw,
                      "staged_eager": ({"achieved": achieved_eager / 1e9, "frac": achieved_eager / HBM_PEAK}

@@ -113,8 +113,9 @@ typedef struct {
   /* Kernel shapes.  With slots = 0 the build times the whole mixed product for every
      combination of the values marked "auto" and keeps the fastest (autotuning). */
   int32_t fft_zblock;     /* z planes interleaved row by row per block in the FFT
-                             work array between the y and z passes: 1 (plain
-                             [z][y][x]) or 8 ([z/8][y][z%8][x]); 0 = auto          */
+                             work array between the y and z passes: B = 1 (plain
+                             [z][y][x]) or a power of two up to 64 and up to Nz
+                             ([z/B][y][z%B][x]); 0 = auto (tuned over 1 and 8)     */
   int32_t rows_per_wave;  /* rows of [Z_i; M_i] one wave of the mixed internal kernel
                              sweeps together: 4 or 8; 0 = auto                     */
   const char* tune_cache; /* path of a text file of autotuning results keyed by

@@ -39,6 +39,12 @@ struct RocHandle {
 
 }  // namespace
 
+static int ilog2(int v) {
+  int k = 0;
+  while ((1 << (k + 1)) <= v) ++k;
+  return k;
+}
+
 // Candidate near triangle pairs (t <= u) in [t0, t1): centroid distance below
 // 1.01 c_near max(diam); the device takes the exact decision.
 std::vector<int32_t> near_candidates(const RWGTable& r, int64_t t0, int64_t t1, double c_near) {
@@ -210,11 +216,13 @@ template <class T> void up(DevBuf& b, const std::vector<T>& v) { b.upload(v); }
 // by substitution on 32-row diagonal blocks.  The interior EFIE matrices at low
 // frequency have pivots spanning about eight decades; explicit inversion of
 // diagonal blocks (as in rocBLAS TRSM) loses all accuracy on such factors,
-// substitution does not.  The updates are two-level: inside a 256-row panel the
-// rows above each solved 32-row block are updated by a narrow GEMM restricted to
-// the panel, and the rows above the panel by one GEMM with inner dimension 256 once
-// the panel is solved, so the large updates read and write X once per 256 solved
-// rows instead of once per 32 (the same sums, grouped differently).
+// substitution does not.  The updates are nested: the rows are cut into panels of
+// 512, those into panels of 128, those into the 32-row blocks; once a panel is
+// solved, the rows above it inside the enclosing panel are updated by one GEMM whose
+// inner dimension is the panel's height.  The large updates thus read and write X
+// once per 512 solved rows (inner dimension 512, compute-bound) instead of once per
+// 32 (memory-bound); the sums are the same, grouped differently.  Every level is
+// reached from n > 512 on.
 // B has nrhs columns (leading dimension n).
 void lu_solve_rhs(rocblas_handle h, int n, double* LU, const rocblas_int* ipiv, double* B, int nrhs, hipStream_t s) {
   auto Z = [](double* p) { return reinterpret_cast<rocblas_double_complex*>(p); };
@@ -227,18 +235,24 @@ void lu_solve_rhs(rocblas_handle h, int n, double* LU, const rocblas_int* ipiv, 
     SLIM_ROC(rocblas_zgemm(h, rocblas_operation_none, rocblas_operation_none, r1 - r0, nrhs, c1 - c0, &mone,
                            Z(LU) + int64_t(c0) * n + r0, n, Z(B) + c0, n, &one, Z(B) + r0, n));
   };
-  const int nb = 32, NB = 256;
-  for (int j1 = n; j1 > 0;) {
-    const int j0 = std::max(0, j1 - NB);
+  // rows [j0, j1), all updates from the rows below j1 applied; level 0 is one block of
+  // at most 32 rows, level k > 0 splits into panels of panel[k - 1] rows from the bottom
+  constexpr int kLevels = 3;
+  static constexpr int panel[kLevels] = {32, 128, 512};
+  auto solve = [&](auto&& self, int j0, int j1, int level) -> void {
+    if (level == 0) {
+      launch_usolve_block(LU, n, j0, j1 - j0, B, n, nrhs, s);
+      return;
+    }
+    const int P = panel[level - 1];
     for (int i1 = j1; i1 > j0;) {
-      const int i0 = std::max(j0, i1 - nb);
-      launch_usolve_block(LU, n, i0, i1 - i0, B, n, nrhs, s);
+      const int i0 = std::max(j0, i1 - P);
+      self(self, i0, i1, level - 1);
       if (i0 > j0) update(j0, i0, i0, i1);
       i1 = i0;
     }
-    if (j0 > 0) update(0, j0, j0, j1);
-    j1 = j0;
-  }
+  };
+  solve(solve, 0, n, kLevels);
 }
 
 void lu_solve(rocblas_handle h, int n, double* LU, const rocblas_int* ipiv, double* B, hipStream_t s) {
@@ -599,7 +613,7 @@ bool tune_cache_lookup(const char* path, const std::string& key, int& per_cu, in
     if (bar == std::string::npos || l.compare(0, bar, key) != 0 || bar != key.size()) continue;
     int a = 0, b = 0, r = 0, z = 0;
     const int got = std::sscanf(l.c_str() + bar, "|per_cu=%d|zblock=%d|rw=%d|z_per_cu=%d", &a, &b, &r, &z);
-    if (got >= 3 && a > 0 && (b == 1 || b == 8) && (r == 4 || r == 8)) {
+    if (got >= 3 && a > 0 && b >= 1 && b <= 64 && (b & (b - 1)) == 0 && (r == 4 || r == 8)) {
       per_cu = a; zb = b; rw = r;
       zpc = got == 4 && z > 0 && z <= a ? z : a;   // older lines: the rows of Z_i on every slot
       found = true;   // the last matching line wins
@@ -635,7 +649,7 @@ static void autotune(Ctx& c, const slim_build_opts& o, hipStream_t s) {
   if (tune_cache_lookup(o.tune_cache, key, per_cu, zb, rw, zpc)) {
     c.slots = per_cu * cus;
     c.slots_z = zpc * cus;
-    c.fft_zsh = zb == 8 ? 3 : 0;
+    c.fft_zsh = ilog2(zb);
     c.rw_mixed = rw;
     pack_tiles(c, pack_mode);
     if (o.verbose)
@@ -664,7 +678,7 @@ static void autotune(Ctx& c, const slim_build_opts& o, hipStream_t s) {
         c.slots_z = k.zpc * cus;
         pack_tiles(c, pack_mode);
       }
-      c.fft_zsh = k.zb == 8 ? 3 : 0;
+      c.fft_zsh = ilog2(k.zb);
       c.rw_mixed = k.rw;
       k.ms = std::min(k.ms, time_product(c, 4));
     }
@@ -677,7 +691,7 @@ static void autotune(Ctx& c, const slim_build_opts& o, hipStream_t s) {
   }
   c.slots = best->per_cu * cus;
   c.slots_z = best->zpc * cus;
-  c.fft_zsh = best->zb == 8 ? 3 : 0;
+  c.fft_zsh = ilog2(best->zb);
   c.rw_mixed = best->rw;
   pack_tiles(c, pack_mode);
   tune_cache_store(o.tune_cache, key, best->per_cu, best->zb, best->rw, best->zpc, best->ms);
@@ -698,6 +712,9 @@ void build_all(Ctx& c, const slim_build_opts& o) {
   SLIM_REQUIRE(!(o.hf_radius > 0.0 && o.precond), SLIM_E_UNSUPPORTED,
                "the conductor-block preconditioner needs the dense Z_i rows: build with precond = 0 when hf_radius > 0");
   SLIM_REQUIRE(o.gen_workers >= 0 && o.gen_workers <= 64, SLIM_E_ARG, "gen_workers must be in [0, 64]");
+  SLIM_REQUIRE(o.fft_zblock == 0 || (o.fft_zblock > 0 && o.fft_zblock <= 64 && (o.fft_zblock & (o.fft_zblock - 1)) == 0),
+               SLIM_E_ARG, "fft_zblock must be 0 or a power of two up to 64");
+  SLIM_REQUIRE(!aim || o.fft_zblock <= o.grid[2], SLIM_E_ARG, "fft_zblock must not exceed the grid's Nz");
   SLIM_HIP(hipSetDevice(c.device));
   c.built = false;
   // A new build starts in free space: the reflected kernels, their spectra and the
@@ -790,10 +807,9 @@ void build_all(Ctx& c, const slim_build_opts& o) {
   c.tile_rows = o.tile_rows > 0 ? o.tile_rows : 64;
   c.sched_mode = o.sched_mode;
   c.drop_graphs();
-  SLIM_REQUIRE(o.fft_zblock == 0 || o.fft_zblock == 1 || o.fft_zblock == 8, SLIM_E_ARG, "fft_zblock must be 0, 1 or 8");
   SLIM_REQUIRE(o.rows_per_wave == 0 || o.rows_per_wave == 4 || o.rows_per_wave == 8, SLIM_E_ARG,
                "rows_per_wave must be 0, 4 or 8");
-  c.fft_zsh = o.fft_zblock == 1 ? 0 : 3;
+  c.fft_zsh = o.fft_zblock > 0 ? ilog2(o.fft_zblock) : 3;
   c.rw_mixed = o.rows_per_wave > 0 ? o.rows_per_wave : 8;
   SLIM_REQUIRE(o.slots_z >= 0, SLIM_E_ARG, "slots_z must be >= 0");
   if (o.slots > 0) {

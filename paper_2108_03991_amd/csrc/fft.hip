@@ -220,10 +220,20 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_pass(PassArgs a) {
 // Fused z step of the free-space convolution: per batch of W adjacent (kx, ky) lines,
 // forward FFT along z, product with the spectrum G^, inverse FFT, lower half kept.
 // G^ is even in kz, so a batch reads its L/2 + 1 distinct values (z-pass layout
-// [ky][kz][kx]: one contiguous stretch per batch) and applies each to kz and L - kz.
-// The component is the fastest grid index, so the workgroups of one batch run
-// together and share its G^ values through L2.  Strided lines as in k_fft_pass
-// (b = line in the batch, fastest).
+// [ky][kz][kx]: one strip per batch) and applies each to kz and L - kz.  Strided lines
+// as in k_fft_pass (b = line in the batch, fastest).
+//
+// Workgroup order, XCD-aware: consecutive workgroups go to the eight XCDs in turn, each
+// with an L2 of its own.  The workgroups that read the same G^ strip -- the components
+// of one batch, the batch whose kx lines mirror it (kx and 2h - kx), and the line
+// whose ky mirrors this one -- get ids that are multiples of eight apart (one XCD) and
+// close in dispatch order, so that the strip comes from HBM once and from L2 after.
+// The strip is loaded with the lines, before the forward transform, which hides its
+// latency, where the registers allow it: holding it across the transform must keep four
+// waves per SIMD (at most 128 VGPRs; the 256-point complex64 and the 1024-point kernels
+// would go above, and load it after the forward transform instead).
+template <class T, int L> constexpr bool early_spectrum() { return !(L == 1024 || (L == 256 && sizeof(T) == 4)); }
+
 template <class T, int L>
 __global__ void __launch_bounds__(kFftThreads) k_fft_zconv(PassArgs a, int ncomp) {
   constexpr int ELEMS = batch_elems<T, false>();
@@ -238,13 +248,41 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_zconv(PassArgs a, int ncomp
   if (TW_LDS)
     for (int e = threadIdx.x; e < L; e += kFftThreads) tw_lds[e] = reinterpret_cast<const C2<T>*>(a.tw)[e];
   const C2<T>* tw = TW_LDS ? tw_lds : reinterpret_cast<const C2<T>*>(a.tw);
-  const int comp = int(blockIdx.x % unsigned(ncomp));
-  const int g1 = int(blockIdx.x / unsigned(ncomp)) * W;
-  const int o2 = blockIdx.y;
+  // batch and component: with nb % 16 == 0 (grid x a multiple of 8, so the XCD of a
+  // workgroup is blockIdx.x % 8 on every grid row), XCD s holds, in dispatch order, the
+  // batches s, nb-1-s, 8+s, nb-9-s, ..., each with all of its components
+  const int nb = int(gridDim.x) / ncomp;
+  int comp, batch;
+  if (nb % 16 == 0) {
+    const int xs = int(blockIdx.x % 8u), t = int(blockIdx.x / 8u);
+    comp = t % ncomp;
+    const int u = t / ncomp, base = 8 * (u / 2) + xs;
+    batch = (u & 1) ? nb - 1 - base : base;
+  } else {
+    comp = int(blockIdx.x % unsigned(ncomp));
+    batch = int(blockIdx.x / unsigned(ncomp));
+  }
+  // line o2: grid rows 2k-1 and 2k take ky = k and its mirror 2h - k (the same G^ row)
+  int o2 = int(blockIdx.y);
+  if (2 * a.h_o2 == int(gridDim.y) && o2 > 0) o2 = (o2 & 1) ? (o2 + 1) / 2 : int(gridDim.y) - o2 / 2;
+  const int g1 = batch * W;
   const C2<T>* in = reinterpret_cast<const C2<T>*>(a.in) + comp * a.comp_in;
   C2<T>* out = reinterpret_cast<C2<T>*>(a.out) + comp * a.comp_out;
   const int64_t in_o2 = boff(o2, a.in_o2, a.in_o2_hi, a.in_o2_sh);
   const int64_t out_o2 = boff(o2, a.out_o2, a.out_o2_hi, a.out_o2_sh);
+  // G^ strip: pair task t = (line b = t % W, kz = t / W), kz in [0, L/2]
+  C2<T> gv[PG];
+  auto load_spectrum = [&]() {
+    const int m2 = o2 <= a.h_o2 ? o2 : 2 * a.h_o2 - o2;
+    const C2<T>* G = reinterpret_cast<const C2<T>*>(a.mul) + int64_t(m2) * a.mul_o2;
+#pragma unroll
+    for (int p = 0; p < PG; ++p) {
+      const int t = threadIdx.x + p * kFftThreads, b = t % W, kz = t / W, o1 = g1 + b;
+      const int m1 = o1 <= a.h_o1 ? o1 : 2 * a.h_o1 - o1;
+      gv[p] = {T(0), T(0)};
+      if (t < NPAIR && o1 < a.n1) gv[p] = G[int64_t(m1) * a.mul_o1 + int64_t(kz) * a.mul_e];
+    }
+  };
   {
     C2<T> v[PER];
 #pragma unroll
@@ -253,6 +291,7 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_zconv(PassArgs a, int ncomp
       v[p] = {T(0), T(0)};
       if (o1 < a.n1 && i < a.n_in) v[p] = ld_stream(in + (o1 * a.in_o1 + in_o2 + boff(i, a.in_e, a.in_e_hi, a.in_e_sh)));
     }
+    if (early_spectrum<T, L>()) load_spectrum();
 #pragma unroll
     for (int p = 0; p < PER; ++p) {
       const int e = threadIdx.x + p * kFftThreads;
@@ -261,25 +300,13 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_zconv(PassArgs a, int ncomp
   }
   __syncthreads();
   fft_batch<T, L, ELEMS, false>(lds, tw);
-  // spectrum product: pair task t = (line b = t % W, kz = t / W), kz in [0, L/2]
-  {
-    const int m2 = o2 <= a.h_o2 ? o2 : 2 * a.h_o2 - o2;
-    const C2<T>* G = reinterpret_cast<const C2<T>*>(a.mul) + int64_t(m2) * a.mul_o2;
-    C2<T> gv[PG];
+  if (!early_spectrum<T, L>()) load_spectrum();
 #pragma unroll
-    for (int p = 0; p < PG; ++p) {
-      const int t = threadIdx.x + p * kFftThreads, b = t % W, kz = t / W, o1 = g1 + b;
-      const int m1 = o1 <= a.h_o1 ? o1 : 2 * a.h_o1 - o1;
-      gv[p] = {T(0), T(0)};
-      if (t < NPAIR && o1 < a.n1) gv[p] = G[int64_t(m1) * a.mul_o1 + int64_t(kz) * a.mul_e];
-    }
-#pragma unroll
-    for (int p = 0; p < PG; ++p) {
-      const int t = threadIdx.x + p * kFftThreads, b = t % W, kz = t / W;
-      if (t < NPAIR) {
-        lds[pidx<L>(b, kz)] = cmul(lds[pidx<L>(b, kz)], gv[p]);
-        if (kz > 0 && kz < L / 2) lds[pidx<L>(b, L - kz)] = cmul(lds[pidx<L>(b, L - kz)], gv[p]);
-      }
+  for (int p = 0; p < PG; ++p) {
+    const int t = threadIdx.x + p * kFftThreads, b = t % W, kz = t / W;
+    if (t < NPAIR) {
+      lds[pidx<L>(b, kz)] = cmul(lds[pidx<L>(b, kz)], gv[p]);
+      if (kz > 0 && kz < L / 2) lds[pidx<L>(b, L - kz)] = cmul(lds[pidx<L>(b, L - kz)], gv[p]);
     }
   }
   __syncthreads();

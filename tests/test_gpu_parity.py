@@ -185,16 +185,20 @@ def test_mesh_and_state_errors(c1_mesh):
 
 
 @pytest.mark.parametrize("N", [(16, 16, 16), (32, 8, 16), (256, 8, 8), (8, 256, 16), (16, 8, 256), (128, 16, 8), (512, 8, 8),
-                               (8, 32, 64), (8, 128, 32), (16, 64, 128)])
-def test_grid_convolution_parity(N):
+                               (8, 32, 64), (8, 128, 32), (16, 64, 128), (256, 8, 128), (512, 8, 64)])
+def test_grid_convolution_parity(N, zblock=0):
     """The FFT convolution H of eq. (11) alone (pruned passes, fused spectrum multiply)
     against the oracle's numpy FFT on the same (anisotropic) grid.  The grids reach every
-    line length the passes are built for, contiguous (x) and strided (y, z): 16 ... 1024."""
+    line length the passes are built for, contiguous (x) and strided (y, z): 16 ... 1024;
+    the last two have 16 or more z-pass batches along x, where the z pass orders its
+    workgroups by XCD (components, mirrored kx batches and mirrored ky lines together)."""
     import torch
     from oracle import aim
     from oracle.operators import Physics
     m = small_boxes(3, seed=4)
-    ctx, lay = context(m, freq=10e9, grid=N)
+    ctx, lay = context(m, freq=10e9, grid=N, fft_zblock=zblock)
+    if zblock:
+        assert lay.fft_zblock == zblock
     grid = aim.make_grid(m.verts, N)
     assert np.allclose(np.array(lay.grid_h), grid.h, rtol=1e-15, atol=0)
     n3 = int(np.prod(N))
@@ -205,6 +209,23 @@ def test_grid_convolution_parity(N):
     for prec, tol in ((FP64, 1e-12), (MIXED, 1e-5)):
         ctx.aim_convolve(prec, torch.tensor(src, device='cuda'), dst, 4)
         assert rel(dst.cpu().numpy(), ref) <= tol
+
+
+@pytest.mark.parametrize("zblock", [1, 16, 64])
+def test_grid_convolution_zblock_layouts(zblock):
+    """The y-to-z work array in every z-block layout [z/B][y][z%B][x]: the same convolution
+    against the oracle, and block sizes that are not powers of two, above 64 or above the
+    grid's Nz are argument errors."""
+    from paper_2108_03991_amd import slim
+    test_grid_convolution_parity((256, 8, 128), zblock)
+    m = small_boxes(3, seed=4)
+    ctx = slim.Context(0)
+    ctx.set_mesh(m.verts, m.tris, m.obj, m.n_obj)
+    for bad, grid in ((3, (16, 16, 16)), (128, (16, 16, 256)), (32, (16, 16, 16))):
+        with pytest.raises(slim.SlimError) as ei:
+            ctx.build(freq=10e9, grid=grid, fft_zblock=bad, precond=0)
+        assert ei.value.code == 1, (bad, grid)
+    ctx.close()
 
 
 def test_graph_replay_matches_eager(boxes_case):
