@@ -90,15 +90,25 @@ __device__ __forceinline__ void stage(C2<T>* lds, int Ns, const C2<T>* tw) {   /
     const int line = it / (L / R), j = it % (L / R);
     const int k = j % Ns;
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      C2<T> x = lds[pidx<L>(line, j + r * (L / R))];
-      if (r > 0 && Ns > 1) {
-        // twiddle index k r L/(Ns R) in [0, L)
-        C2<T> w = tw[(k * r * (L / (Ns * R))) % L];
-        if (INV) w.y = -w.y;
-        x = cmul(x, w);
+    for (int r = 0; r < R; ++r) v[p][r] = lds[pidx<L>(line, j + r * (L / R))];
+    if (Ns > 1) {
+      // twiddles w^r, w = e^{-+2 pi i k / (Ns R)} = table entry k L/(Ns R): one table
+      // read, the powers by products (depth log2 R), in place of R - 1 reads
+      C2<T> w[R];
+      w[1] = tw[k * (L / (Ns * R))];
+      if (INV) w[1].y = -w[1].y;
+      if (R >= 4) {
+        w[2] = cmul(w[1], w[1]);
+        w[3] = cmul(w[2], w[1]);
       }
-      v[p][r] = x;
+      if (R == 8) {
+        w[4] = cmul(w[2], w[2]);
+        w[5] = cmul(w[4], w[1]);
+        w[6] = cmul(w[4], w[2]);
+        w[7] = cmul(w[4], w[3]);
+      }
+#pragma unroll
+      for (int r = 1; r < R; ++r) v[p][r] = cmul(v[p][r], w[r]);
     }
     dftR<R, T, INV>(v[p]);
     outb[p] = (line << 16) | ((j / Ns) * Ns * R + k);
