@@ -77,7 +77,11 @@ constexpr int kFftThreads = 512;
 template <int L> constexpr int line_stride() { return L + L / 8 + 1; }
 template <int L> __device__ __forceinline__ int pidx(int b, int i) { return b * line_stride<L>() + i + (i >> 3); }
 
-template <class T, int L, int R, int ELEMS, bool INV>
+// HIN: the upper half of each line is zero and only the lower half is read (a first
+// stage, Ns = 1: input r of a butterfly is at j + r L/R, in the upper half for r >= R/2);
+// HOUT: only the lower half of the result is written (a last stage, Ns = L/R: output r
+// goes to k + r Ns).
+template <class T, int L, int R, int ELEMS, bool INV, bool HIN = false, bool HOUT = false>
 __device__ __forceinline__ void stage(C2<T>* lds, int Ns, const C2<T>* tw) {   // tw: the L twiddles
   constexpr int NB = ELEMS / R;           // butterflies in the batch
   constexpr int PER = NB / kFftThreads;   // per thread
@@ -90,7 +94,8 @@ __device__ __forceinline__ void stage(C2<T>* lds, int Ns, const C2<T>* tw) {   /
     const int line = it / (L / R), j = it % (L / R);
     const int k = j % Ns;
 #pragma unroll
-    for (int r = 0; r < R; ++r) v[p][r] = lds[pidx<L>(line, j + r * (L / R))];
+    for (int r = 0; r < R; ++r)
+      v[p][r] = (HIN && r >= R / 2) ? C2<T>{T(0), T(0)} : lds[pidx<L>(line, j + r * (L / R))];
     if (Ns > 1) {
       // twiddles w^r, w = e^{-+2 pi i k / (Ns R)} = table entry k L/(Ns R): one table
       // read, the powers by products (depth log2 R), in place of R - 1 reads
@@ -117,17 +122,20 @@ __device__ __forceinline__ void stage(C2<T>* lds, int Ns, const C2<T>* tw) {   /
 #pragma unroll
   for (int p = 0; p < PER; ++p)
 #pragma unroll
-    for (int r = 0; r < R; ++r) lds[pidx<L>(outb[p] >> 16, (outb[p] & 0xffff) + r * Ns)] = v[p][r];
+    for (int r = 0; r < R; ++r)
+      if (!HOUT || r < R / 2) lds[pidx<L>(outb[p] >> 16, (outb[p] & 0xffff) + r * Ns)] = v[p][r];
   __syncthreads();
 }
 
-template <class T, int L, int ELEMS, bool INV>
-__device__ void fft_batch(C2<T>* lds, const C2<T>* tw) {
-  int Ns = 1;
-  int rem = L;
-  while (rem >= 8) { stage<T, L, 8, ELEMS, INV>(lds, Ns, tw); Ns *= 8; rem /= 8; }
-  if (rem == 4) { stage<T, L, 4, ELEMS, INV>(lds, Ns, tw); Ns *= 4; rem /= 4; }
-  if (rem == 2) { stage<T, L, 2, ELEMS, INV>(lds, Ns, tw); }
+// The stages of a batch: radix 8 while at least 8 points remain per sub-transform, then
+// one of radix 4 or 2.  HIN (zero-padded input: the upper half of every line is zero)
+// prunes the first stage, HOUT (only the lower half of the result is kept) the last.
+template <class T, int L, int ELEMS, bool INV, bool HIN = false, bool HOUT = false, int NS = 1>
+__device__ __forceinline__ void fft_batch(C2<T>* lds, const C2<T>* tw) {
+  constexpr int REM = L / NS;
+  constexpr int R = REM >= 8 ? 8 : REM;
+  stage<T, L, R, ELEMS, INV, HIN && NS == 1, HOUT && NS * R == L>(lds, NS, tw);
+  if constexpr (NS * R < L) fft_batch<T, L, ELEMS, INV, HIN, HOUT, NS * R>(lds, tw);
 }
 
 // Offset of index i along an axis of stride lo; a blocked axis (sh > 0) splits i into
@@ -169,9 +177,12 @@ template <class T> __device__ __forceinline__ void st_stream(C2<T>* p, C2<T> v) 
 // workgroups fit the LDS of a compute unit.
 template <class T, bool CONTIG> constexpr int batch_elems() { return (sizeof(T) == 4 && !CONTIG) ? 8192 : 4096; }
 
-template <class T, int L, bool CONTIG, int MODE>
+// HALF: a forward pass (MODE 0) whose lines are zero-padded to twice their length
+// (n_in = L/2), or an inverse pass (MODE 1) that keeps the lower half (n_out = L/2).
+template <class T, int L, bool CONTIG, int MODE, bool HALF>
 __global__ void __launch_bounds__(kFftThreads) k_fft_pass(PassArgs a) {
   constexpr int ELEMS = batch_elems<T, CONTIG>();
+  constexpr bool HIN = HALF && MODE == 0, HOUT = HALF && MODE == 1;
   constexpr int W = ELEMS / L;
   extern __shared__ unsigned char smem_raw[];
   C2<T>* lds = reinterpret_cast<C2<T>*>(smem_raw);
@@ -211,12 +222,11 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_pass(PassArgs a) {
     for (int p = 0; p < PER; ++p) {
       int b, i;
       coords(p, b, i);
-      lds[pidx<L>(b, i)] = v[p];
+      if (!HIN || i < L / 2) lds[pidx<L>(b, i)] = v[p];   // the zero half is never read
     }
   }
   __syncthreads();
-  if (MODE == 1) fft_batch<T, L, ELEMS, true>(lds, tw);
-  else fft_batch<T, L, ELEMS, false>(lds, tw);
+  fft_batch<T, L, ELEMS, MODE == 1, HIN, HOUT>(lds, tw);
 #pragma unroll
   for (int p = 0; p < PER; ++p) {
     int b, i;
@@ -238,11 +248,11 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_pass(PassArgs a) {
 // of one batch, the batch whose kx lines mirror it (kx and 2h - kx), and the line
 // whose ky mirrors this one -- get ids that are multiples of eight apart (one XCD) and
 // close in dispatch order, so that the strip comes from HBM once and from L2 after.
-// The strip is loaded with the lines, before the forward transform, which hides its
-// latency, where the registers allow it: holding it across the transform must keep four
-// waves per SIMD (at most 128 VGPRs; the 256-point complex64 and the 1024-point kernels
-// would go above, and load it after the forward transform instead).
-template <class T, int L> constexpr bool early_spectrum() { return !(L == 1024 || (L == 256 && sizeof(T) == 4)); }
+// In complex128 the strip is loaded with the lines, before the forward transform, which
+// hides its latency; holding it across the transform must keep four waves per SIMD (at
+// most 128 VGPRs), which the complex64 kernels (twice the lines per batch) and the
+// 1024-point ones would exceed: they load it after the forward transform.
+template <class T, int L> constexpr bool early_spectrum() { return sizeof(T) == 8 && L < 1024; }
 
 template <class T, int L>
 __global__ void __launch_bounds__(kFftThreads) k_fft_zconv(PassArgs a, int ncomp) {
@@ -305,11 +315,11 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_zconv(PassArgs a, int ncomp
 #pragma unroll
     for (int p = 0; p < PER; ++p) {
       const int e = threadIdx.x + p * kFftThreads;
-      lds[pidx<L>(e % W, e / W)] = v[p];
+      if (e / W < L / 2) lds[pidx<L>(e % W, e / W)] = v[p];   // zero-padded upper half: never read
     }
   }
   __syncthreads();
-  fft_batch<T, L, ELEMS, false>(lds, tw);
+  fft_batch<T, L, ELEMS, false, true, false>(lds, tw);
   if (!early_spectrum<T, L>()) load_spectrum();
 #pragma unroll
   for (int p = 0; p < PG; ++p) {
@@ -320,7 +330,7 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_zconv(PassArgs a, int ncomp
     }
   }
   __syncthreads();
-  fft_batch<T, L, ELEMS, true>(lds, tw);
+  fft_batch<T, L, ELEMS, true, false, true>(lds, tw);   // the lower half is kept
 #pragma unroll
   for (int p = 0; p < PER; ++p) {
     const int e = threadIdx.x + p * kFftThreads, b = e % W, i = e / W, o1 = g1 + b;
@@ -331,6 +341,7 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_zconv(PassArgs a, int ncomp
 
 template <class T>
 void launch_zconv_L(int L, const PassArgs& a, int ncomp, hipStream_t s) {
+  SLIM_REQUIRE(2 * a.n_in == L && 2 * a.n_out == L, SLIM_E_STATE, "fused z pass: lines must be zero-padded to 2 Nz");
   constexpr int ELEMS = batch_elems<T, false>();
   const size_t shm = size_t((ELEMS / L) * (L + L / 8 + 1) + (sizeof(T) == 4 ? L : 0)) * sizeof(C2<T>);
   const int W = ELEMS / L;
@@ -355,8 +366,8 @@ void launch_zconv_L(int L, const PassArgs& a, int ncomp, hipStream_t s) {
   SLIM_HIP(hipGetLastError());
 }
 
-template <class T, bool CONTIG, int MODE>
-void launch_pass_L(int L, const PassArgs& a, int ncomp, hipStream_t s) {
+template <class T, bool CONTIG, int MODE, bool HALF>
+void launch_pass_LH(int L, const PassArgs& a, int ncomp, hipStream_t s) {
   constexpr int ELEMS = batch_elems<T, CONTIG>();
   const size_t shm = size_t((ELEMS / L) * (L + L / 8 + 1) + (sizeof(T) == 4 ? L : 0)) * sizeof(C2<T>);
   const int W = ELEMS / L;
@@ -366,11 +377,11 @@ void launch_pass_L(int L, const PassArgs& a, int ncomp, hipStream_t s) {
   case LL: {                                                                                                  \
     static bool attr_set = false;                                                                             \
     if (!attr_set) { /* more than 64 KB of dynamic LDS needs the explicit limit */                            \
-      SLIM_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fft_pass<T, LL, CONTIG, MODE>),           \
+      SLIM_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fft_pass<T, LL, CONTIG, MODE, HALF>),     \
                                    hipFuncAttributeMaxDynamicSharedMemorySize, int(shm)));                     \
       attr_set = true;                                                                                        \
     }                                                                                                         \
-    hipLaunchKernelGGL((k_fft_pass<T, LL, CONTIG, MODE>), grid, dim3(kFftThreads), shm, s, a);                \
+    hipLaunchKernelGGL((k_fft_pass<T, LL, CONTIG, MODE, HALF>), grid, dim3(kFftThreads), shm, s, a);          \
     break;                                                                                                    \
   }
     SLIM_FFT_CASE(16) SLIM_FFT_CASE(32) SLIM_FFT_CASE(64) SLIM_FFT_CASE(128) SLIM_FFT_CASE(256)
@@ -379,6 +390,15 @@ void launch_pass_L(int L, const PassArgs& a, int ncomp, hipStream_t s) {
     default: throw Error(SLIM_E_UNSUPPORTED, "FFT length " + std::to_string(L) + " (2N must be a power of two in [16, 1024])");
   }
   SLIM_HIP(hipGetLastError());
+}
+
+// Pruned form when the lines are zero-padded to L (forward) or only their lower half is
+// kept (inverse), as in every pass of the convolution; full transforms otherwise.
+template <class T, bool CONTIG, int MODE>
+void launch_pass_L(int L, const PassArgs& a, int ncomp, hipStream_t s) {
+  const bool half = MODE == 0 ? 2 * a.n_in == L : 2 * a.n_out == L;
+  if (half) launch_pass_LH<T, CONTIG, MODE, true>(L, a, ncomp, s);
+  else launch_pass_LH<T, CONTIG, MODE, false>(L, a, ncomp, s);
 }
 
 // Spectrum product of the layered medium on the full-z spectra of the four
