@@ -444,11 +444,21 @@ TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "hbm_traffic_internal_conductors
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2108_03991_amd", "csrc", "kernels.hip")
 
 
+def internal_kernel_source():
+    """Source text of the internal kernel: its work-queue helpers through the end of
+    k_internal in kernels.hip (what the traffic record's hash covers)."""
+    s = open(KERNEL_SOURCE).read()
+    a = s.index("struct TileQueue {")
+    k = s.index("k_internal(const float2*", a)
+    return s[a:s.index("\n}\n", k) + 3]
+
+
 def internal_traffic(workload, lay):
     """HBM bytes per launch of the internal kernel from the committed counter summary:
     FETCH_SIZE and WRITE_SIZE (KiB per dispatch) times the copy-kernel calibration factors.
-    None when the summary is for another workload or shape, or when the kernel source has
-    changed since the counters were taken (its SHA-256 is part of the record)."""
+    None when the summary is for another workload or shape, or when the kernel's source
+    has changed since the counters were taken (the SHA-256 of that source is part of the
+    record)."""
     import hashlib
     try:
         rec = None
@@ -457,8 +467,8 @@ def internal_traffic(workload, lay):
                 rec = json.loads(line[len("traffic-record: "):])
         if rec is None or rec.get("workload") != workload or rec.get("internal_entries") != lay.internal_entries:
             return None
-        sha = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
-        if rec.get("kernels_hip_sha256") != sha:
+        sha = hashlib.sha256(internal_kernel_source().encode()).hexdigest()
+        if rec.get("kernel_source_sha256") != sha:
             return None
         return 1024.0 * (rec["fetch_kib"] * rec["fetch_factor"] + rec["write_kib"] * rec["write_factor"])
     except (OSError, ValueError, KeyError):

@@ -666,7 +666,9 @@ __global__ void __launch_bounds__(256) k_rows_A(const int32_t* we_base, const vo
     const C2<T> pp = phi[tplus[m]], pm = phi[tminus[m]];
     double yr = -k0 * double(si) + l * (double(pp.x) - double(pm.x));
     double yi = k0 * double(sr) + l * (double(pp.y) - double(pm.y));
-    for (int q = 0; q < 4; ++q) {
+    // without e (ev null) the I_x e / eta0 term is left to k_add_ix_e, which adds it in
+    // the same order, so the result is the same to the bit
+    for (int q = 0; e && q < 4; ++q) {
       const int c = ix_col[4 * m + q];
       if (c < 0) continue;
       const C2<T> ec = e[c];
@@ -675,6 +677,25 @@ __global__ void __launch_bounds__(256) k_rows_A(const int32_t* we_base, const vo
     }
     y[m] = make_double2(yr, yi);
   }
+}
+
+// y1 += I_x e / eta0: the last term of the RWG rows, once the rows of Z_i are done
+template <bool F64>
+__global__ void k_add_ix_e(const int32_t* __restrict__ ix_col, const double* __restrict__ ix_val, const void* ev,
+                           double inv_eta0, double2* __restrict__ y, int64_t n_e) {
+  using T = typename P<F64>::T;
+  const int64_t m = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (m >= n_e) return;
+  const C2<T>* e = reinterpret_cast<const C2<T>*>(ev);
+  double2 v = y[m];
+  for (int q = 0; q < 4; ++q) {
+    const int c = ix_col[4 * m + q];
+    if (c < 0) continue;
+    const C2<T> ec = e[c];
+    v.x += inv_eta0 * ix_val[4 * m + q] * double(ec.x);
+    v.y += inv_eta0 * ix_val[4 * m + q] * double(ec.y);
+  }
+  y[m] = v;
 }
 
 // y2 = F D j + j k0 c0rho = -(1/A_t) sum_i s_i l_i j_i + j k0 c0rho_t
@@ -904,13 +925,16 @@ void matvec_t(Ctx& c, const void* x, void* y, void* e_out, void* g_out, void* a_
       SLIM_HIP(hipGetLastError());
     }
     mark(3);
-    if (overlap_z) SLIM_HIP(hipStreamWaitEvent(s, c.ev_zjoin, 0));
     mark(4);
+    // with the rows of Z_i still running beside, the RWG rows take everything but the
+    // I_x e / eta0 term now (their near-field and interpolation reads overlap the tail of
+    // that launch) and the term is added once e is complete
     hipLaunchKernelGGL((k_rows_A<F64, true>), dim3(nblk(ne, 16)), dim3(256), 0, s, c.d_we_base.as<int32_t>(),
                        F64 ? c.d_we_w64.p : c.d_we_w32.p, c.d_oct_out.p, N3, Nx, NxNy, c.d_nA_ptr.as<int64_t>(),
                        c.d_nA_col.as<int32_t>(), F64 ? c.d_nA_v128.p : c.d_nA_v64.p, jv, nullptr, c.d_phi.p,
-                       ev, c.d_tplus.as<int32_t>(), c.d_tminus.as<int32_t>(), c.d_len.as<double>(),
-                       c.d_ix_col.as<int32_t>(), c.d_ix_val.as<double>(), c.k0, inv_eta0, c.d_a.p, Y, ne);
+                       overlap_z ? nullptr : ev, c.d_tplus.as<int32_t>(), c.d_tminus.as<int32_t>(),
+                       c.d_len.as<double>(), c.d_ix_col.as<int32_t>(), c.d_ix_val.as<double>(), c.k0, inv_eta0,
+                       c.d_a.p, Y, ne);
     mark(4);
   }
   SLIM_HIP(hipGetLastError());
@@ -920,6 +944,12 @@ void matvec_t(Ctx& c, const void* x, void* y, void* e_out, void* g_out, void* a_
                      Y + ne, nt);
   SLIM_HIP(hipGetLastError());
   mark(5);
+  if (overlap_z) {
+    SLIM_HIP(hipStreamWaitEvent(s, c.ev_zjoin, 0));
+    hipLaunchKernelGGL(k_add_ix_e<F64>, dim3(nblk(ne)), dim3(256), 0, s, c.d_ix_col.as<int32_t>(),
+                       c.d_ix_val.as<double>(), ev, inv_eta0, Y, ne);
+    SLIM_HIP(hipGetLastError());
+  }
   auto out = [&](const void* src, void* dst, int64_t n) {
     if (!dst) return;
     hipLaunchKernelGGL(k_copy_out<F64>, dim3(nblk(n)), dim3(256), 0, s, src, reinterpret_cast<double2*>(dst), n);
