@@ -384,7 +384,11 @@ void build_aim(Ctx& c, hipStream_t s) {
   upv(d_cidxE, SE.cidx);
   upv(d_cidxT, ST.cidx);
   // ---- near field: exact entries, precorrection ----
-  for (int which = 0; which < 2; ++which) {
+  // L_phi first: its pass keeps the vector-potential integrals of its triangle pairs (when
+  // the memory allows), which the L_A pass then reads instead of recomputing the pairs
+  // its RWG pairs share (each triangle pair serves up to nine RWG pairs)
+  DevBuf ia_tab;
+  for (int which : {1, 0}) {
     const bool rwg = which == 0;
     std::vector<int64_t> ptr;
     std::vector<int32_t> col;
@@ -409,6 +413,23 @@ void build_aim(Ctx& c, hipStream_t s) {
     na.rows = d_rows.as<int32_t>(); na.cols = d_col.as<int32_t>(); na.nnz = nnz;
     na.kr = c.k0; na.ki = 0.0;
     na.out = v128.as<double>();
+    if (!rwg) {
+      size_t freeb = 0, totalb = 0;
+      SLIM_HIP(hipMemGetInfo(&freeb, &totalb));
+      const size_t need = size_t(nnz) * 18 * sizeof(double);
+      if (nnz > 0 && need + (size_t(8) << 30) < freeb) {
+        try {
+          ia_tab.alloc(need);
+        } catch (const Error&) {
+          ia_tab.release();   // the table is an optimisation: without it L_A computes every pair
+        }
+      }
+      na.ia = ia_tab.p ? ia_tab.as<double>() : nullptr;
+    } else if (ia_tab.p) {
+      na.ia = ia_tab.as<double>();
+      na.tp_ptr = c.d_nP_ptr.as<int64_t>();
+      na.tp_col = c.d_nP_col.as<int32_t>();
+    }
     launch_near_entries(na, rwg, s);
     PreArgs pa{};
     pa.rows = d_rows.as<int32_t>(); pa.cols = d_col.as<int32_t>(); pa.nnz = nnz;

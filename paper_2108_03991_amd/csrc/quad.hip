@@ -526,6 +526,17 @@ __device__ void tri_pair_oriented(const NearArgs& g, int t, int u, Cx IA[9], Cx&
   }
 }
 
+// position of column u in row t of a CSR with sorted columns, or -1
+__device__ __forceinline__ int64_t csr_find(const int64_t* ptr, const int32_t* col, int t, int u) {
+  int64_t lo = ptr[t], hi = ptr[t + 1];
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (col[mid] < u) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo < ptr[t + 1] && col[lo] == u ? lo : -1;
+}
+
 __global__ void __launch_bounds__(64) k_near_LA(NearArgs g) {
   const int64_t z = blockIdx.x;
   if (z >= g.nnz) return;
@@ -536,16 +547,25 @@ __global__ void __launch_bounds__(64) k_near_LA(NearArgs g) {
   for (int a = 0; a < 2; ++a)
     for (int b = 0; b < 2; ++b) {
       const int t = tm[a], u = tn[b];
-      Cx IA[9], IS;
-      tri_pair_oriented(g, t, u, IA, IS);
       int i = 0, j = 0;
       for (int k = 0; k < 3; ++k) {
         if (g.tri_edge[3 * t + k] == m) i = k;
         if (g.tri_edge[3 * u + k] == n) j = k;
       }
+      // the same oriented integrals as tri_pair_oriented computes, from the table when
+      // the L_phi pattern holds (t, u) (every lane takes the same branch)
+      const int64_t pos = g.ia ? csr_find(g.tp_ptr, g.tp_col, t, u) : -1;
+      Cx v;
+      if (pos >= 0) {
+        v = {g.ia[18 * pos + 2 * (3 * i + j)], g.ia[18 * pos + 2 * (3 * i + j) + 1]};
+      } else {
+        Cx IA[9], IS;
+        tri_pair_oriented(g, t, u, IA, IS);
+        v = IA[3 * i + j];
+      }
       double cv = g.tri_sign[3 * t + i] * g.tri_sign[3 * u + j] * g.len[m] * g.len[n] / (4.0 * g.area[t] * g.area[u]);
-      accr += cv * IA[3 * i + j].r;
-      acci += cv * IA[3 * i + j].i;
+      accr += cv * v.r;
+      acci += cv * v.i;
     }
   if ((threadIdx.x & 63) == 0) {
     g.out[2 * z] = accr;
@@ -562,6 +582,11 @@ __global__ void __launch_bounds__(64) k_near_Lphi(NearArgs g) {
   if ((threadIdx.x & 63) == 0) {
     g.out[2 * z] = IS.r / (g.area[t] * g.area[u]);
     g.out[2 * z + 1] = IS.i / (g.area[t] * g.area[u]);
+    if (g.ia)
+      for (int k = 0; k < 9; ++k) {
+        g.ia[18 * z + 2 * k] = IA[k].r;
+        g.ia[18 * z + 2 * k + 1] = IA[k].i;
+      }
   }
 }
 
@@ -573,6 +598,7 @@ void launch_near_entries(const NearArgs& g, bool rwg, hipStream_t s) {
   for (int64_t lo = 0; lo < g.nnz; lo += chunk) {
     NearArgs h = g;
     h.rows += lo; h.cols += lo; h.out += 2 * lo;
+    if (h.ia && !rwg) h.ia += 18 * lo;   // the L_phi pass writes its chunk's rows of the table
     h.nnz = std::min(chunk, g.nnz - lo);
     if (rwg) hipLaunchKernelGGL(k_near_LA, dim3(unsigned(h.nnz)), dim3(64), 0, s, h);
     else hipLaunchKernelGGL(k_near_Lphi, dim3(unsigned(h.nnz)), dim3(64), 0, s, h);

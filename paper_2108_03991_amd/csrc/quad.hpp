@@ -47,6 +47,13 @@ struct NearArgs {
   int64_t nnz;
   double kr, ki;
   double* out;                                // complex128 values
+  // triangle-pair table (optional): the L_phi pass writes the oriented vector-potential
+  // integrals IA (3 x 3 complex) of each of its pairs at ia + 18 z; the L_A pass looks its
+  // triangle pairs up in that pattern (CSR tp_ptr / tp_col over triangle rows) and
+  // computes only the pairs it does not hold
+  double* ia = nullptr;
+  const int64_t* tp_ptr = nullptr;
+  const int32_t* tp_col = nullptr;
 };
 void launch_near_entries(const NearArgs& g, bool rwg, hipStream_t s);
 
