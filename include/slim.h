@@ -373,8 +373,9 @@ slim_status slim_rhs_planewave(slim_ctx* ctx, const double khat[3], const double
 /* GMRES on S A x = S b with S = diag(1/h^2 (N_E rows), h (N_T rows)), h the
  * mean edge length (a change of length unit that balances the two row blocks),
  * right-preconditioned by the conductor blocks when opts.use_precond = 1.
- * x_dev: in = x0, out = solution (complex128, n_sys).  b_dev is S b or b
- * according to `scaled_rhs` (1: b_dev already equilibrated).  Synchronous. */
+ * x_dev: in = x0, out = solution (complex128, n_sys); a zero x0 takes no product for
+ * its first residual (S b).  b_dev is S b or b according to `scaled_rhs` (1: b_dev
+ * already equilibrated).  Synchronous. */
 slim_status slim_solve(slim_ctx* ctx, const void* b_dev, int32_t scaled_rhs, void* x_dev,
                        const slim_solve_opts* opts, slim_solve_info* info, void* stream);
 

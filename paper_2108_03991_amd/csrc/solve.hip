@@ -155,7 +155,8 @@ struct Krylov {
     SLIM_HIP(hipMemcpyAsync(out.data(), hdev.p, size_t(nv) * 16, hipMemcpyDeviceToHost, s));
     SLIM_HIP(hipStreamSynchronize(s));
   }
-  double norm(const double2* vec) {
+  // sum of |vec_i|^2 (NaN if an entry is not finite)
+  double sumsq(const double2* vec) {
     // use the multidot machinery with V_0 := vec
     hipLaunchKernelGGL(k_multidot, dim3(kDotBlocks), dim3(256), 0, s, vec, n, 1, vec, n, partial.as<double2>());
     hipLaunchKernelGGL(k_reduce_partial, dim3(1), dim3(256), 0, s, partial.as<double2>(), kDotBlocks, 1,
@@ -164,8 +165,9 @@ struct Krylov {
     cd v;
     SLIM_HIP(hipMemcpyAsync(&v, hdev.p, 16, hipMemcpyDeviceToHost, s));
     SLIM_HIP(hipStreamSynchronize(s));
-    return std::sqrt(std::max(0.0, v.real()));
+    return v.real();
   }
+  double norm(const double2* vec) { return std::sqrt(std::max(0.0, sumsq(vec))); }
   // out = S A v with the given precision
   void op(slim_prec p, const double2* v, double2* out) {
     matvec(c, p, v, out, nullptr, nullptr, nullptr, nullptr, s);
@@ -268,10 +270,15 @@ slim_status solve_gmres(Ctx& c, const void* b, int scaled_rhs, void* x, const sl
   double rel = 1.0;
   DevBuf d;
   d.alloc(size_t(K.n) * 16);
+  // a zero initial guess has A x = 0: the first residual needs no product (K.y is zero)
+  bool x_zero = K.sumsq(reinterpret_cast<const double2*>(x)) == 0.0;
   while (true) {
     // true residual with the FP64 operator
-    matvec(c, SLIM_FP64, X, K.y.p, nullptr, nullptr, nullptr, nullptr, s);
-    info.n_matvec_fp64++;
+    if (!x_zero) {
+      matvec(c, SLIM_FP64, X, K.y.p, nullptr, nullptr, nullptr, nullptr, s);
+      info.n_matvec_fp64++;
+    }
+    x_zero = false;
     hipLaunchKernelGGL(k_scaled_residual, dim3(nblk(K.n)), dim3(256), 0, s, B, K.y.as<double2>(), K.r.as<double2>(),
                        K.ne, K.n, K.s1, K.s2, scaled_rhs);
     SLIM_HIP(hipGetLastError());
