@@ -208,7 +208,7 @@ __global__ void __launch_bounds__(256) k_internal(const float2* __restrict__ hi,
                                                   unsigned long long* __restrict__ stamps,
                                                   unsigned long long* __restrict__ span) {
   using T = typename P<F64>::T;
-  // RW rows per wave per sweep (4 in FP64, where hi + lo doubles the loads; 4 or 8 in mixed)
+  // RW rows per wave per sweep (chosen at the launch: 2 in FP64, where hi + lo doubles the loads; 4 or 8 in mixed)
   const C2<T>* H = reinterpret_cast<const C2<T>*>(Hv);
   C2<T>* e = reinterpret_cast<C2<T>*>(ev);
   C2<T>* jo = reinterpret_cast<C2<T>*>(jv);
@@ -823,7 +823,7 @@ void internal_launch(Ctx& c, const void* H, void* e, void* j, void* g, hipStream
     hipLaunchKernelGGL(kern, dim3(nwg), dim3(256), 0, s, c.d_hi.as<float2>(), c.d_lo.as<float2>(),
                        c.d_blocks.as<BlockDev>(), q, H, e, j, g, st, sp);
   };
-  if (F64) go(k_internal<true, 4>);
+  if (F64) go(k_internal<true, 2>);   // two rows per wave: 120 VGPRs, four waves per SIMD
   else if (c.rw_mixed == 4) go(k_internal<false, 4>);
   else go(k_internal<false, 8>);
   SLIM_HIP(hipGetLastError());
