@@ -148,7 +148,8 @@ typedef struct {
  * z block and rows per wave, graphs on, no tuning cache).
  * Autotuning (slots = 0) times the whole mixed product for 2, 4 and 8 persistent
  * internal workgroups per compute unit, times the "auto" kernel shapes, times the
- * workgroups of the launch of the rows of Z_i (as many, or one per compute unit),
+ * workgroups of the launch of the rows of Z_i (as many, or, under dynamic dispatch
+ * (sched_mode 3 or 4), one per compute unit),
  * at build time and keeps the fastest.  A tuning cache entry for the same shape
  * skips the timing.  With slots > 0 nothing is timed: auto shapes take 64 and 8,
  * and both launches use `slots` workgroups.                                      */

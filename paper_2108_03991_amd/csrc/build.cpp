@@ -663,14 +663,16 @@ static void autotune(Ctx& c, const slim_build_opts& o, hipStream_t s) {
   std::vector<int> rws = o.rows_per_wave > 0 ? std::vector<int>{c.rw_mixed} : std::vector<int>{4, 8};
   const int per_cu_set[3] = {2, 4, 8};
   // workgroups of the launch of the rows of Z_i, which runs beside the projection and FFT
-  // of j: as many as the other launch, or one per CU (room for the FFT's workgroups)
+  // of j: as many as the other launch, or one per CU (room for the FFT's workgroups).  One
+  // per CU only under dynamic dispatch: static queues packed for so few workgroups leave a
+  // long tail, and only there can the FP64 launch take the M rows' count instead
   struct Cand { int per_cu, zb, rw, zpc; double ms; };
   std::vector<Cand> cand;
   for (int pc : per_cu_set)
     for (int z : zbs)
       for (int r : rws)
         for (int zpc : {pc, 1})
-          if (zpc == pc || !c.plain) cand.push_back({pc, z, r, zpc, 1e300});
+          if (zpc == pc || (!c.plain && pack_mode == 3)) cand.push_back({pc, z, r, zpc, 1e300});
   for (int round = 0; round < 2; ++round)
     for (Cand& k : cand) {
       if (k.per_cu * cus != c.slots || k.zpc * cus != c.zslots()) {
