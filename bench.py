@@ -456,9 +456,9 @@ def internal_kernel_source():
 def internal_traffic(workload, lay):
     """HBM bytes per launch of the internal kernel from the committed counter summary:
     FETCH_SIZE and WRITE_SIZE (KiB per dispatch) times the copy-kernel calibration factors.
-    None when the summary is for another workload or shape, or when the kernel's source
-    has changed since the counters were taken (the SHA-256 of that source is part of the
-    record)."""
+    None when the summary is for another workload, shape or rows-per-wave instantiation, or
+    when the kernel's source has changed since the counters were taken (the SHA-256 of that
+    source is part of the record)."""
     import hashlib
     try:
         rec = None
@@ -466,6 +466,8 @@ def internal_traffic(workload, lay):
             if line.startswith("traffic-record: "):
                 rec = json.loads(line[len("traffic-record: "):])
         if rec is None or rec.get("workload") != workload or rec.get("internal_entries") != lay.internal_entries:
+            return None
+        if rec.get("rows_per_wave") != lay.rows_per_wave:
             return None
         sha = hashlib.sha256(internal_kernel_source().encode()).hexdigest()
         if rec.get("kernel_source_sha256") != sha:
