@@ -117,7 +117,8 @@ typedef struct {
                              [z][y][x]) or a power of two up to 64 and up to Nz
                              ([z/B][y][z%B][x]); 0 = auto (tuned over 1 and 8)     */
   int32_t rows_per_wave;  /* rows of [Z_i; M_i] one wave of the mixed internal kernel
-                             sweeps together: 4 or 8; 0 = auto                     */
+                             sweeps together: 4 or 8; 0 = auto (the FP64 kernel,
+                             which reads hi + lo, always sweeps two)               */
   const char* tune_cache; /* path of a text file of autotuning results keyed by
                              (kernel, shape, gfx950), read before and appended after
                              tuning; NULL = no cache                               */
@@ -173,7 +174,7 @@ typedef struct {
   int64_t precond_entries;             /* stored complex64 entries (rows x ext)   */
   int64_t precond_cap;                 /* cap in effect (0: every conductor whole) */
   int32_t fft_zblock;                  /* kernel shapes in effect (tuned or given) */
-  int32_t rows_per_wave;
+  int32_t rows_per_wave;               /* of the mixed internal kernel               */
   int64_t z_nnz;                       /* stored entries of the sparse Z~ (hf_radius > 0),
                                           0 with dense interior operators           */
   int32_t slots_z;                     /* persistent workgroups of the launch of the rows of
