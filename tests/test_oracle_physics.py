@@ -121,7 +121,7 @@ def test_passivity(c1_system, c1_mesh):
     (I_x) leaves one mode per mesh vertex that carries (almost) no power, and there the
     discretisation puts eigenvalues slightly below zero.  Their size does not fall under
     refinement (about -1.5 % of the largest on a cube at 1, 2 and 3 divisions per side,
-    10 GHz), so the pin bounds the count of such modes and the power they carry: the bar
+    10 GHz), so the pin fixes the count of such modes and bounds the power they carry: the bar
     has exactly N_V = 298 of them at 1, 10 and 100 GHz, separated from the positive ones
     (largest negative -3e-6, smallest positive 1.6e-2 of the largest eigenvalue), together
     0.17 % of the positive power at 10 GHz; a flipped sign of Z makes 590 modes negative."""
@@ -131,7 +131,7 @@ def test_passivity(c1_system, c1_mesh):
     Q = (Q + Q.conj().T) / 2
     ev = np.linalg.eigvalsh(Q)
     neg = ev[ev < 0]
-    assert neg.size <= len(c1_mesh.verts)
+    assert neg.size == len(c1_mesh.verts)
     assert -neg.sum() <= 5e-3 * ev[ev > 0].sum()
     assert ev.min() >= -1e-2 * ev.max()
 
