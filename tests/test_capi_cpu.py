@@ -86,3 +86,21 @@ def test_layered_gammas_match_oracle():
             assert np.abs(ge - ref_e).max() <= 1e-12 and np.abs(gh - ref_h).max() <= 1e-12, (layers, bottom, f)
     with pytest.raises(slim.SlimError):
         slim.layered_gammas([(-1.0, 4.0, 0.0)], "pec", 1e9, kr)
+
+
+def test_every_context_entry_point_rejects_a_null_context():
+    """Each entry point that takes a context returns SLIM_E_ARG for NULL, whatever the
+    other arguments (zero or NULL here), and touches nothing."""
+    import ctypes as C
+    from paper_2108_03991_amd import slim
+    L = slim.lib()
+    header = open(__file__.replace('tests/test_capi_cpu.py', 'include/slim.h')).read()
+    names = re.findall(r'slim_status\s+(slim_[a-z_0-9]+)\s*\(\s*slim_ctx\s*\*', header)
+    assert len(names) >= 20 and "slim_sched_set_shape" in names and "slim_create" not in names
+    for name in names:
+        f = getattr(L, name)
+        assert f.argtypes, name        # every exported call is declared in the binding
+        args = [None]
+        for t in f.argtypes[1:]:
+            args.append(0.0 if t in (C.c_double, C.c_float) else (0 if t in (C.c_int32, C.c_int64) else None))
+        assert f(*args) == 1, name
